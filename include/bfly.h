@@ -1,0 +1,170 @@
+/*
+ * bfly.h -- C ABI of the MI355X butterfly library (libbfly.so).
+ *
+ * The library applies the butterfly algorithm of Poulson, Demanet, Maxwell &
+ * Ying, "A Parallel Butterfly Algorithm", to kernels K(x, y) = exp(i Phi(x, y))
+ * with a smooth real phase Phi (Sec. 2, Eq. "phase"), using analytic
+ * tensor-product Chebyshev interpolation (Sec. 2 "Avoiding quadratic
+ * precomputation"):
+ *
+ *   f(x) ~= sum_y exp(i Phi(x, y)) g(y)            (Sec. 1, Eq. 1 over all boxes)
+ *
+ * evaluated in O(r^2 N^d log N) work (Sec. 1) on one GPU.  The steps are the
+ * sequential algorithm's (Alg. "alg:serial"): leaf initialisation, log2 N
+ * merge-and-split stages (Sec. 1.1) with the column-to-row "middle switch"
+ * at stage floor(log2 N / 2), and final evaluation at the targets.
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ *  - Phi = 2 pi tau; the phase ids below define tau, the phase in turns.
+ *  - Points are row-major FP64 [n][d] arrays in DEVICE memory, any order.
+ *  - Values are complex128 (interleaved re, im doubles) in DEVICE memory;
+ *    right-hand side k of g starts at g + 2*k*ldg doubles (ldg >= n_src).
+ *    Input and output are complex128 in every precision mode.
+ *  - The caller owns every device buffer, including the workspace.  No entry
+ *    point allocates device memory, and apply calls never synchronise: all
+ *    work is enqueued on `stream` (a hipStream_t; NULL = default stream).
+ *    Buffers must stay valid until that work completes.
+ *  - Errors are return codes; nothing is thrown.  Argument validation happens
+ *    on the host, before any HIP call, so invalid arguments never reach the
+ *    GPU.  A device error from earlier asynchronous work is reported as
+ *    BFLY_EDEVICE by the next call.  bfly_last_error() returns a
+ *    thread-local message describing the last failure.
+ *  - Points outside the plan's boxes are clamped into the nearest leaf box;
+ *    NaN coordinates go to leaf 0.  Accuracy degrades gracefully there.
+ *  - The plan does not check the butterfly condition (Sec. 1: diam(A)
+ *    diam(B) <= D for every interacting pair); choosing N for the boxes and
+ *    phase is the caller's job.
+ *  - Plans are immutable and hold no device memory; one plan may be used
+ *    concurrently on several streams with distinct workspaces.
+ */
+#ifndef BFLY_H
+#define BFLY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bfly_plan_s* bfly_plan_t;
+
+/* status codes */
+enum {
+  BFLY_OK = 0,
+  BFLY_EINVAL = 1,       /* an argument is out of range or NULL                */
+  BFLY_EUNSUPPORTED = 2, /* valid, but not supported (e.g. phase id for this d) */
+  BFLY_ENOMEM = 3,       /* host allocation failed                              */
+  BFLY_EDEVICE = 4,      /* a HIP call or earlier device work failed            */
+  BFLY_EWORKSPACE = 5    /* workspace missing or smaller than required          */
+};
+
+/* phase ids (tau = Phi / 2 pi; N is the plan's N)
+ *  FOURIER      tau = x . y                                  any d  (Sec. 4)
+ *  HYPRADON2    tau = N x0 sqrt(y0^2 + x1^2 y1^2)            d = 2  (Sec. 4.1 family)
+ *  GENRADON3    tau = N (x.y + sqrt(g0^2 y0^2 + g1^2 y1^2 + y2^2)),
+ *               g0 = (2 + sin 2pi x0 sin 2pi x1)/3,
+ *               g1 = (2 + cos 2pi x0 cos 2pi x1)/3           d = 3  (Sec. 4.2 family)
+ *  SEPARABLE_TEST tau = N (sum_j x_j^2 + sum_j y_j^3)        any d  (rank-one kernel:
+ *               the butterfly is exact, used to check results at any size) */
+enum {
+  BFLY_PHASE_FOURIER = 0,
+  BFLY_PHASE_HYPRADON2 = 1,
+  BFLY_PHASE_GENRADON3 = 2,
+  BFLY_PHASE_SEPARABLE_TEST = 3
+};
+
+/* precision modes (internal arithmetic; I/O is always complex128)
+ *  FP64   everything in FP64 (the paper computes in double precision, Sec. 4).
+ *  FP32   phase tau and its reduction modulo 1 in FP64, then FP32
+ *         sine/cosine, FP32 weights and FP32 contractions. */
+enum { BFLY_FP64 = 0, BFLY_FP32 = 1 };
+
+/* Create a plan.
+ *  d        1, 2 or 3
+ *  N        leaf boxes per dimension, a power of two, 1 <= N, N^d < 2^31
+ *  src_lo/src_hi  host double[d]: source box Y = prod [lo, hi), hi > lo, finite
+ *  tgt_lo/tgt_hi  host double[d]: target box X
+ *  phase_id one of BFLY_PHASE_*, valid for d
+ *  q        Chebyshev nodes per dimension (rank r = q^d):
+ *           d = 1: 2..16, d = 2: 2..16, d = 3: 2..6
+ *  out      receives the plan (host object; no device memory, no HIP call)
+ * Returns BFLY_OK, BFLY_EINVAL, BFLY_EUNSUPPORTED or BFLY_ENOMEM. */
+int bfly_plan(int d, int64_t N, const double* src_lo, const double* src_hi,
+              const double* tgt_lo, const double* tgt_hi, int phase_id, int q,
+              bfly_plan_t* out);
+
+/* Destroy a plan (NULL is accepted).  Returns BFLY_OK. */
+int bfly_plan_destroy(bfly_plan_t plan);
+
+/* Query a plan: out[0..4] = d, N, q, r = q^d, switch level floor(log2 N / 2).
+ * Returns BFLY_OK or BFLY_EINVAL. */
+int bfly_plan_info(bfly_plan_t plan, int64_t* out5);
+
+/* Device workspace, in bytes, needed by one apply (forward or adjoint) with
+ * n_in input points, nrhs right-hand sides and precision prec.  n_in is
+ * n_src for bfly_apply and n_tgt for bfly_apply_adjoint.  May call into
+ * HIP to size library sort storage; never allocates.
+ * Returns BFLY_OK, BFLY_EINVAL or BFLY_EDEVICE. */
+int bfly_workspace_size(bfly_plan_t plan, int64_t n_in, int nrhs, int prec, size_t* bytes);
+
+/* Forward apply f = B g  (B ~= K restricted to the points).
+ *  n_src, y   sources, device double[n_src][d]            (n_src >= 0)
+ *  g, ldg     device complex128 [nrhs][ldg], ldg >= n_src
+ *  n_tgt, x   targets, device double[n_tgt][d]            (n_tgt >= 0)
+ *  f, ldf     device complex128 [nrhs][ldf], ldf >= n_tgt; entries
+ *             [k][0..n_tgt) are overwritten, in the caller's target order
+ *  nrhs       1 .. 4096
+ *  prec       BFLY_FP64 or BFLY_FP32
+ *  ws         device workspace of ws_bytes >= bfly_workspace_size(plan, n_src, nrhs, prec)
+ *  stream     hipStream_t (NULL = default stream)
+ * f must not alias g, x, y or ws.
+ * Returns BFLY_OK, BFLY_EINVAL, BFLY_EWORKSPACE or BFLY_EDEVICE. */
+int bfly_apply(bfly_plan_t plan,
+               int64_t n_src, const double* y, const void* g, int64_t ldg,
+               int64_t n_tgt, const double* x, void* f, int64_t ldf,
+               int nrhs, int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint apply g_out = B' f_in, where B' is the butterfly for the adjoint
+ * kernel K^H(y, x) = exp(-i Phi(x, y)): the same steps with the roles of
+ * the two point sets swapped and the phase negated (Sec. 1: the low-rank
+ * condition is symmetric in diam(A) diam(B)).  B' approximates K^H to the
+ * same accuracy; it is not the exact transpose of B.
+ *  n_tgt, x       the plan's targets (now the inputs), device double[n_tgt][d]
+ *  f_in, ldf      device complex128 [nrhs][ldf], ldf >= n_tgt
+ *  n_src, y       the plan's sources (now the outputs), device double[n_src][d]
+ *  g_out, ldg     device complex128 [nrhs][ldg], ldg >= n_src, overwritten
+ *  ws             ws_bytes >= bfly_workspace_size(plan, n_tgt, nrhs, prec)
+ * Other arguments and returns as bfly_apply. */
+int bfly_apply_adjoint(bfly_plan_t plan,
+                       int64_t n_tgt, const double* x, const void* f_in, int64_t ldf,
+                       int64_t n_src, const double* y, void* g_out, int64_t ldg,
+                       int nrhs, int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* Per-step timing, for profiling.  While enabled, every apply records a HIP
+ * event pair around each kernel launch on its stream (a few microseconds of
+ * overhead per launch).  bfly_timing_read waits for the recorded events,
+ * writes the accumulated milliseconds and launch counts per step kind since
+ * the previous read, and resets them.  Step kinds (BFLY_STEP_*):
+ *   0 binning (leaf keys, sort, CSR offsets)   1 initialisation
+ *   2 first-half stages                         3 middle switch
+ *   4 second-half stages                        5 final evaluation
+ * ms and launches are host arrays of BFLY_NUM_STEPS entries.  The timing
+ * state is process-wide; do not enable it while several threads apply.
+ * Returns BFLY_OK, BFLY_EINVAL or BFLY_EDEVICE. */
+enum { BFLY_NUM_STEPS = 6 };
+int bfly_timing_enable(int on);
+int bfly_timing_read(double* ms, int64_t* launches);
+
+/* Static description of a status code. */
+const char* bfly_status_string(int status);
+
+/* Thread-local detail message of the last failing call on this thread
+ * ("" if none). */
+const char* bfly_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFLY_H */

@@ -1,0 +1,12 @@
+"""MI355X-native butterfly apply for oscillatory kernels K(x, y) = exp(i Phi(x, y)).
+
+Implements the butterfly algorithm of Poulson, Demanet, Maxwell & Ying, "A
+Parallel Butterfly Algorithm" (sequential form, Alg. "alg:serial", with the
+analytic Chebyshev interpolation of Sec. 2) as HIP kernels for gfx950 behind
+the C ABI of include/bfly.h.  This package is the Python binding
+(``bfly.py``), the build script (``build.py``) and the seeded synthetic
+workloads (``workloads.py``).
+"""
+from .bfly import (BFLY_FP32, BFLY_FP64, BflyError, Plan, bfly_apply, bfly_apply_adjoint,  # noqa: F401
+                   bfly_apply_autograd, bfly_last_error, bfly_plan, bfly_plan_destroy, bfly_plan_info,
+                   bfly_status_string, bfly_timing_enable, bfly_timing_read, bfly_workspace_size, lib)

@@ -1,0 +1,272 @@
+"""Python binding of libbfly (include/bfly.h): argument marshalling only.
+
+Every step of the butterfly apply runs in the HIP kernels of libbfly.so;
+PyTorch supplies device memory and the stream.  There is no CPU fallback:
+importing the binding without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbfly.so")
+
+BFLY_OK, BFLY_EINVAL, BFLY_EUNSUPPORTED, BFLY_ENOMEM, BFLY_EDEVICE, BFLY_EWORKSPACE = range(6)
+BFLY_PHASE_FOURIER, BFLY_PHASE_HYPRADON2, BFLY_PHASE_GENRADON3, BFLY_PHASE_SEPARABLE_TEST = range(4)
+BFLY_FP64, BFLY_FP32 = 0, 1
+
+PHASES = {"fourier": 0, "hypradon2": 1, "genradon3": 2, "separable": 3}
+PRECISIONS = {"fp64": BFLY_FP64, "fp32": BFLY_FP32}
+
+EXPORTS = ("bfly_plan", "bfly_plan_destroy", "bfly_plan_info", "bfly_workspace_size", "bfly_apply",
+           "bfly_apply_adjoint", "bfly_timing_enable", "bfly_timing_read", "bfly_status_string",
+           "bfly_last_error")
+STEP_NAMES = ("binning", "init", "stage_src", "switch", "stage_tgt", "final")
+
+
+class BflyError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libbfly.so (built by ``python -m paper_1305_4650_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1305_4650_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64
+    L.bfly_plan.restype = ctypes.c_int
+    L.bfly_plan.argtypes = [ctypes.c_int, i64, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int,
+                            ctypes.POINTER(vp)]
+    L.bfly_plan_destroy.restype = ctypes.c_int
+    L.bfly_plan_destroy.argtypes = [vp]
+    L.bfly_plan_info.restype = ctypes.c_int
+    L.bfly_plan_info.argtypes = [vp, ctypes.POINTER(i64)]
+    L.bfly_workspace_size.restype = ctypes.c_int
+    L.bfly_workspace_size.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.bfly_apply.restype = ctypes.c_int
+    L.bfly_apply.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp, i64, ctypes.c_int, ctypes.c_int, vp,
+                             ctypes.c_size_t, vp]
+    L.bfly_apply_adjoint.restype = ctypes.c_int
+    L.bfly_apply_adjoint.argtypes = L.bfly_apply.argtypes
+    L.bfly_timing_enable.restype = ctypes.c_int
+    L.bfly_timing_enable.argtypes = [ctypes.c_int]
+    L.bfly_timing_read.restype = ctypes.c_int
+    L.bfly_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    L.bfly_status_string.restype = ctypes.c_char_p
+    L.bfly_status_string.argtypes = [ctypes.c_int]
+    L.bfly_last_error.restype = ctypes.c_char_p
+    L.bfly_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str):
+    if rc != BFLY_OK:
+        raise BflyError(rc, where, lib().bfly_last_error().decode() or bfly_status_string(rc))
+
+
+def _darr(v, d):
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(d))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ----------------------------------------------------------------------------
+# the C ABI, one Python function per entry point
+# ----------------------------------------------------------------------------
+
+def bfly_plan(d: int, N: int, src_lo, src_hi, tgt_lo, tgt_hi, phase_id: int, q: int) -> int:
+    bufs = [_darr(v, d) for v in (src_lo, src_hi, tgt_lo, tgt_hi)]
+    out = ctypes.c_void_p()
+    _check(lib().bfly_plan(d, N, *[b[1] for b in bufs], phase_id, q, ctypes.byref(out)), "bfly_plan")
+    return out.value
+
+
+def bfly_plan_destroy(plan: int) -> None:
+    _check(lib().bfly_plan_destroy(plan), "bfly_plan_destroy")
+
+
+def bfly_plan_info(plan: int) -> dict:
+    out = (ctypes.c_int64 * 5)()
+    _check(lib().bfly_plan_info(plan, out), "bfly_plan_info")
+    return dict(zip(("d", "N", "q", "r", "switch_level"), list(out)))
+
+
+def bfly_workspace_size(plan: int, n_in: int, nrhs: int, prec: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().bfly_workspace_size(plan, n_in, nrhs, prec, ctypes.byref(out)), "bfly_workspace_size")
+    return out.value
+
+
+def bfly_apply(plan, n_src, y, g, ldg, n_tgt, x, f, ldf, nrhs, prec, ws, ws_bytes, stream) -> None:
+    _check(lib().bfly_apply(plan, n_src, y, g, ldg, n_tgt, x, f, ldf, nrhs, prec, ws, ws_bytes, stream),
+           "bfly_apply")
+
+
+def bfly_apply_adjoint(plan, n_tgt, x, f_in, ldf, n_src, y, g_out, ldg, nrhs, prec, ws, ws_bytes,
+                       stream) -> None:
+    _check(lib().bfly_apply_adjoint(plan, n_tgt, x, f_in, ldf, n_src, y, g_out, ldg, nrhs, prec, ws,
+                                    ws_bytes, stream), "bfly_apply_adjoint")
+
+
+def bfly_timing_enable(on: bool) -> None:
+    _check(lib().bfly_timing_enable(int(bool(on))), "bfly_timing_enable")
+
+
+def bfly_timing_read() -> dict:
+    """{step name: (milliseconds, launches)} accumulated since the last read."""
+    ms = (ctypes.c_double * len(STEP_NAMES))()
+    n = (ctypes.c_int64 * len(STEP_NAMES))()
+    _check(lib().bfly_timing_read(ms, n), "bfly_timing_read")
+    return {k: (ms[i], n[i]) for i, k in enumerate(STEP_NAMES)}
+
+
+def bfly_status_string(status: int) -> str:
+    return lib().bfly_status_string(status).decode()
+
+
+def bfly_last_error() -> str:
+    return lib().bfly_last_error().decode()
+
+
+# ----------------------------------------------------------------------------
+# torch-facing convenience (device buffers and streams from PyTorch)
+# ----------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _prec_id(prec) -> int:
+    return PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+
+
+def _points(t, d, name):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if t.dim() != 2 or t.shape[1] != d or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous ({'n'}, {d}) tensor")
+    return t
+
+
+def _values(t, n, name):
+    """(nrhs, n) complex128 with unit stride along points -> (tensor, leading dimension)."""
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128):
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if t.dim() == 1:
+        t = t.unsqueeze(0)
+    if t.dim() != 2 or t.shape[1] != n or (n > 1 and t.stride(1) != 1):
+        raise ValueError(f"{name} must be (nrhs, {n}) with unit stride along points")
+    ld = t.stride(0) if t.shape[0] > 1 else max(n, 1)
+    if ld < n:
+        raise ValueError(f"{name}: rows overlap")
+    return t, max(ld, 1)
+
+
+class Plan:
+    """A butterfly plan: d, N, source box, target box, phase, q."""
+
+    def __init__(self, d: int, N: int, src_box, tgt_box, phase, q: int):
+        self.d, self.N, self.q = int(d), int(N), int(q)
+        self.phase_id = PHASES[phase] if isinstance(phase, str) else int(phase)
+        self.src_box = (np.asarray(src_box[0], float), np.asarray(src_box[1], float))
+        self.tgt_box = (np.asarray(tgt_box[0], float), np.asarray(tgt_box[1], float))
+        self.handle = bfly_plan(self.d, self.N, self.src_box[0], self.src_box[1], self.tgt_box[0],
+                                self.tgt_box[1], self.phase_id, self.q)
+        self.info = bfly_plan_info(self.handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.bfly_plan_destroy(h)
+            self.handle = None
+
+    def workspace_size(self, n_in: int, nrhs: int, prec="fp64") -> int:
+        return bfly_workspace_size(self.handle, n_in, nrhs, _prec_id(prec))
+
+    def workspace(self, n_in: int, nrhs: int, prec="fp64", device=None):
+        torch = _torch()
+        nbytes = self.workspace_size(n_in, nrhs, prec)
+        return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device or "cuda")
+
+    def _run(self, adjoint, pin, vin, pout, prec, out, workspace, stream):
+        torch = _torch()
+        d = self.d
+        pin = _points(pin, d, "input points")
+        pout = _points(pout, d, "output points")
+        n_in, n_out = pin.shape[0], pout.shape[0]
+        vin, ldin = _values(vin, n_in, "input values")
+        nrhs = vin.shape[0]
+        p = _prec_id(prec)
+        if out is None:
+            out = torch.empty((nrhs, n_out), dtype=torch.complex128, device=pin.device)
+        out2, ldout = _values(out, n_out, "output values")
+        if out2.shape[0] != nrhs:
+            raise ValueError("output has the wrong number of right-hand sides")
+        nbytes = self.workspace_size(n_in, nrhs, p)
+        if workspace is None:
+            workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=pin.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(pin.device).cuda_stream
+        fn = bfly_apply_adjoint if adjoint else bfly_apply
+        fn(self.handle, n_in, pin.data_ptr(), vin.data_ptr(), ldin, n_out, pout.data_ptr(),
+           out2.data_ptr(), ldout, nrhs, p, workspace.data_ptr(), workspace.numel(), stream)
+        return out
+
+    def apply(self, y, g, x, prec="fp64", out=None, workspace=None, stream=None):
+        """f = B g: sources y (n_src, d), g (nrhs, n_src) -> f (nrhs, n_tgt) at targets x."""
+        return self._run(False, y, g, x, prec, out, workspace, stream)
+
+    def apply_adjoint(self, x, f, y, prec="fp64", out=None, workspace=None, stream=None):
+        """g = B' f with B' the butterfly of K^H (roles swapped, phase -Phi)."""
+        return self._run(True, x, f, y, prec, out, workspace, stream)
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class BflyApply(torch.autograd.Function):
+        """f = B g with backward grad_g = B' grad_f (the adjoint butterfly).
+
+        The map is linear, so nothing per level is saved; the vector-Jacobian
+        product of f = K g for complex g is K^H grad_f, which the adjoint
+        butterfly approximates to the same accuracy as B approximates K."""
+
+        @staticmethod
+        def forward(ctx, g, plan, y, x, prec="fp64"):
+            ctx.plan, ctx.prec = plan, prec
+            ctx.save_for_backward(y, x)
+            return plan.apply(y, g.contiguous(), x, prec)
+
+        @staticmethod
+        def backward(ctx, grad_f):
+            y, x = ctx.saved_tensors
+            g = ctx.plan.apply_adjoint(x, grad_f.contiguous(), y, ctx.prec)
+            return g, None, None, None, None
+
+    return BflyApply
+
+
+_BflyApply = None
+
+
+def bfly_apply_autograd(g, plan: Plan, y, x, prec="fp64"):
+    """Differentiable forward apply (see BflyApply)."""
+    global _BflyApply
+    if _BflyApply is None:
+        _BflyApply = _make_autograd()
+    return _BflyApply.apply(g, plan, y, x, prec)

@@ -1,0 +1,281 @@
+// Host side of libbfly: argument validation (before any HIP call), plans,
+// workspace sizing and carving, and the C ABI of include/bfly.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/bfly.h"
+#include "bfly_internal.h"
+
+struct bfly_plan_s {
+  int d = 0;
+  int64_t N = 0;
+  int L = 0;
+  int q = 0;
+  int r = 0;
+  int phase = 0;
+  double src_lo[3] = {0, 0, 0}, src_hi[3] = {0, 0, 0};
+  double tgt_lo[3] = {0, 0, 0}, tgt_hi[3] = {0, 0, 0};
+  double z[bfly::kQMax] = {};
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int ok() {
+  g_last_error.clear();
+  return BFLY_OK;
+}
+
+int q_max(int d) { return d == 3 ? 6 : 16; }
+
+constexpr size_t kAlign = 256;
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Geometry of one apply in its own roles (adjoint swaps the boxes).
+bfly::Geo make_geo(const bfly_plan_s& p, bool adjoint) {
+  bfly::Geo g;
+  std::memset(&g, 0, sizeof g);
+  g.d = p.d;
+  g.L = p.L;
+  g.q = p.q;
+  g.r = p.r;
+  g.ls = p.L / 2;
+  g.phase = p.phase;
+  g.adj = adjoint ? 1 : 0;
+  g.nc = 1 << p.d;
+  g.Nd = (double)p.N;
+  const double* slo = adjoint ? p.tgt_lo : p.src_lo;
+  const double* shi = adjoint ? p.tgt_hi : p.src_hi;
+  const double* tlo = adjoint ? p.src_lo : p.tgt_lo;
+  const double* thi = adjoint ? p.src_hi : p.tgt_hi;
+  for (int j = 0; j < p.d; ++j) {
+    g.slo[j] = slo[j];
+    g.sD[j] = shi[j] - slo[j];
+    g.tlo[j] = tlo[j];
+    g.tD[j] = thi[j] - tlo[j];
+  }
+  for (int k = 0; k < p.q; ++k) g.z[k] = p.z[k];
+  return g;
+}
+
+struct Layout {
+  size_t w, keys, keys_sorted, idx, perm, offs, tmp, total;
+  size_t tmp_bytes;
+};
+
+int layout(const bfly_plan_s& p, int64_t n_in, int nrhs, int prec, Layout* out) {
+  bfly::Geo g = make_geo(p, false);
+  size_t tmp_bytes = 0;
+  hipError_t e = bfly::sort_storage_bytes(n_in, p.d * p.L, &tmp_bytes);
+  if (e != hipSuccess) return fail(BFLY_EDEVICE, "sort storage query failed: %s", hipGetErrorString(e));
+  const size_t n = (size_t)(n_in > 0 ? n_in : 0);
+  const size_t P = (size_t)1 << (p.d * p.L);
+  Layout L;
+  size_t off = 0;
+  L.w = off;
+  off += up(bfly::weight_bytes(g, nrhs, prec));
+  L.keys = off;
+  off += up(4 * n);
+  L.keys_sorted = off;
+  off += up(4 * n);
+  L.idx = off;
+  off += up(4 * n);
+  L.perm = off;
+  off += up(4 * n);
+  L.offs = off;
+  off += up(4 * (P + 1));
+  L.tmp = off;
+  off += up(tmp_bytes);
+  L.total = off;
+  L.tmp_bytes = tmp_bytes;
+  *out = L;
+  return BFLY_OK;
+}
+
+int check_plan(const bfly_plan_s* p) {
+  if (!p) return fail(BFLY_EINVAL, "plan is NULL");
+  return BFLY_OK;
+}
+
+int check_sticky() {
+  hipError_t e = hipPeekAtLastError();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BFLY_EDEVICE, "earlier device work failed: %s", hipGetErrorString(e));
+  }
+  return BFLY_OK;
+}
+
+int apply_common(bfly_plan_t plan, bool adjoint, int64_t n_in, const double* pin, const void* vin,
+                 int64_t ldin, int64_t n_out, const double* pout, void* vout, int64_t ldout, int nrhs,
+                 int prec, void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  const char* nin = adjoint ? "n_tgt" : "n_src";
+  const char* nout = adjoint ? "n_src" : "n_tgt";
+  if (n_in < 0 || n_in >= ((int64_t)1 << 31)) return fail(BFLY_EINVAL, "%s out of range", nin);
+  if (n_out < 0 || n_out >= ((int64_t)1 << 31)) return fail(BFLY_EINVAL, "%s out of range", nout);
+  if (nrhs < 1 || nrhs > 4096) return fail(BFLY_EINVAL, "nrhs must be in [1, 4096]");
+  if (prec != BFLY_FP64 && prec != BFLY_FP32) return fail(BFLY_EINVAL, "unknown precision mode %d", prec);
+  if (ldin < n_in || ldin < 1) return fail(BFLY_EINVAL, "leading dimension of the input < number of inputs");
+  if (ldout < n_out || ldout < 1) return fail(BFLY_EINVAL, "leading dimension of the output < number of outputs");
+  if (n_in > 0 && (!pin || !vin)) return fail(BFLY_EINVAL, "input points or values are NULL");
+  if (n_out > 0 && (!pout || !vout)) return fail(BFLY_EINVAL, "output points or values are NULL");
+  Layout L;
+  if (int rc = layout(*plan, n_in, nrhs, prec, &L)) return rc;
+  if (!ws || ws_bytes < L.total)
+    return fail(BFLY_EWORKSPACE, "workspace of %zu bytes given, %zu required", ws ? ws_bytes : (size_t)0,
+                L.total);
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(BFLY_EINVAL, "workspace must be 256-byte aligned");
+  if (int rc = check_sticky()) return rc;
+  char* base = static_cast<char*>(ws);
+  bfly::Work w;
+  w.W = base + L.w;
+  w.keys = reinterpret_cast<uint32_t*>(base + L.keys);
+  w.keys_sorted = reinterpret_cast<uint32_t*>(base + L.keys_sorted);
+  w.idx = reinterpret_cast<int32_t*>(base + L.idx);
+  w.perm = reinterpret_cast<int32_t*>(base + L.perm);
+  w.offs = reinterpret_cast<int32_t*>(base + L.offs);
+  w.sort_tmp = base + L.tmp;
+  w.sort_tmp_bytes = L.tmp_bytes;
+  bfly::Geo g = make_geo(*plan, adjoint);
+  hipError_t e = bfly::run_apply(g, prec, n_in, pin, static_cast<const double*>(vin), ldin, n_out, pout,
+                                 static_cast<double*>(vout), ldout, nrhs, w, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(BFLY_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int bfly_plan(int d, int64_t N, const double* src_lo, const double* src_hi, const double* tgt_lo,
+              const double* tgt_hi, int phase_id, int q, bfly_plan_t* out) {
+  if (!out) return fail(BFLY_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (d < 1 || d > 3) return fail(BFLY_EINVAL, "d must be 1, 2 or 3 (got %d)", d);
+  if (N < 1 || (N & (N - 1)) != 0) return fail(BFLY_EINVAL, "N must be a power of two >= 1");
+  int L = 0;
+  while (((int64_t)1 << L) < N) ++L;
+  if ((int64_t)d * L > 30) return fail(BFLY_EINVAL, "N^d must be below 2^31");
+  if (q < 2 || q > q_max(d)) return fail(BFLY_EINVAL, "q must be in [2, %d] for d = %d", q_max(d), d);
+  if (!src_lo || !src_hi || !tgt_lo || !tgt_hi) return fail(BFLY_EINVAL, "box corner pointer is NULL");
+  for (int j = 0; j < d; ++j) {
+    if (!std::isfinite(src_lo[j]) || !std::isfinite(src_hi[j]) || !(src_hi[j] > src_lo[j]))
+      return fail(BFLY_EINVAL, "source box must be finite with hi > lo in every dimension");
+    if (!std::isfinite(tgt_lo[j]) || !std::isfinite(tgt_hi[j]) || !(tgt_hi[j] > tgt_lo[j]))
+      return fail(BFLY_EINVAL, "target box must be finite with hi > lo in every dimension");
+  }
+  if (phase_id < 0 || phase_id > 3) return fail(BFLY_EINVAL, "unknown phase id %d", phase_id);
+  if (phase_id == BFLY_PHASE_HYPRADON2 && d != 2) return fail(BFLY_EUNSUPPORTED, "HYPRADON2 needs d = 2");
+  if (phase_id == BFLY_PHASE_GENRADON3 && d != 3) return fail(BFLY_EUNSUPPORTED, "GENRADON3 needs d = 3");
+  bfly_plan_s* p = new (std::nothrow) bfly_plan_s;
+  if (!p) return fail(BFLY_ENOMEM, "plan allocation failed");
+  p->d = d;
+  p->N = N;
+  p->L = L;
+  p->q = q;
+  p->r = 1;
+  for (int j = 0; j < d; ++j) p->r *= q;
+  p->phase = phase_id;
+  for (int j = 0; j < d; ++j) {
+    p->src_lo[j] = src_lo[j];
+    p->src_hi[j] = src_hi[j];
+    p->tgt_lo[j] = tgt_lo[j];
+    p->tgt_hi[j] = tgt_hi[j];
+  }
+  // Chebyshev nodes of the first kind (the grid of Sec. 2)
+  for (int k = 0; k < q; ++k) p->z[k] = std::cos((double)(2 * k + 1) * M_PI / (double)(2 * q));
+  *out = p;
+  return ok();
+}
+
+int bfly_plan_destroy(bfly_plan_t plan) {
+  delete plan;
+  return ok();
+}
+
+int bfly_plan_info(bfly_plan_t plan, int64_t* out5) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!out5) return fail(BFLY_EINVAL, "out is NULL");
+  out5[0] = plan->d;
+  out5[1] = plan->N;
+  out5[2] = plan->q;
+  out5[3] = plan->r;
+  out5[4] = plan->L / 2;
+  return ok();
+}
+
+int bfly_workspace_size(bfly_plan_t plan, int64_t n_in, int nrhs, int prec, size_t* bytes) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!bytes) return fail(BFLY_EINVAL, "bytes is NULL");
+  if (n_in < 0 || n_in >= ((int64_t)1 << 31)) return fail(BFLY_EINVAL, "n_in out of range");
+  if (nrhs < 1 || nrhs > 4096) return fail(BFLY_EINVAL, "nrhs must be in [1, 4096]");
+  if (prec != BFLY_FP64 && prec != BFLY_FP32) return fail(BFLY_EINVAL, "unknown precision mode %d", prec);
+  Layout L;
+  if (int rc = layout(*plan, n_in, nrhs, prec, &L)) return rc;
+  *bytes = L.total;
+  return ok();
+}
+
+int bfly_apply(bfly_plan_t plan, int64_t n_src, const double* y, const void* g, int64_t ldg, int64_t n_tgt,
+               const double* x, void* f, int64_t ldf, int nrhs, int prec, void* ws, size_t ws_bytes,
+               void* stream) {
+  return apply_common(plan, false, n_src, y, g, ldg, n_tgt, x, f, ldf, nrhs, prec, ws, ws_bytes, stream);
+}
+
+int bfly_apply_adjoint(bfly_plan_t plan, int64_t n_tgt, const double* x, const void* f_in, int64_t ldf,
+                       int64_t n_src, const double* y, void* g_out, int64_t ldg, int nrhs, int prec, void* ws,
+                       size_t ws_bytes, void* stream) {
+  return apply_common(plan, true, n_tgt, x, f_in, ldf, n_src, y, g_out, ldg, nrhs, prec, ws, ws_bytes, stream);
+}
+
+int bfly_timing_enable(int on) {
+  bfly::timing_set(on != 0);
+  return ok();
+}
+
+int bfly_timing_read(double* ms, int64_t* launches) {
+  if (!ms || !launches) return fail(BFLY_EINVAL, "output arrays are NULL");
+  hipError_t e = bfly::timing_read(ms, launches);
+  if (e != hipSuccess) return fail(BFLY_EDEVICE, "timing events failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+const char* bfly_status_string(int status) {
+  switch (status) {
+    case BFLY_OK:
+      return "success";
+    case BFLY_EINVAL:
+      return "invalid argument";
+    case BFLY_EUNSUPPORTED:
+      return "unsupported configuration";
+    case BFLY_ENOMEM:
+      return "host allocation failed";
+    case BFLY_EDEVICE:
+      return "device error";
+    case BFLY_EWORKSPACE:
+      return "workspace too small";
+    default:
+      return "unknown status";
+  }
+}
+
+const char* bfly_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

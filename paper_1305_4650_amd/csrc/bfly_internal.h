@@ -1,0 +1,70 @@
+// Internal declarations shared by the host API and the kernel launchers of
+// libbfly.  Not installed; the public interface is include/bfly.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace bfly {
+
+constexpr int kQMax = 16;
+
+// Geometry and phase of one apply, in the roles of that apply: for the
+// adjoint the plan's target box plays the source role and vice versa, and
+// `adj` negates and transposes the phase.  Passed to kernels by value.
+struct Geo {
+  int d, L, q, r;      // dimension, log2 N, nodes per dim, q^d
+  int ls, phase, adj;  // switch level, phase id, adjoint flag
+  int nc;              // 2^d
+  double Nd;           // N as a double (scale inside the phase)
+  double slo[3], sD[3];  // source-role box: lower corner, extent
+  double tlo[3], tD[3];  // target-role box
+  double z[kQMax];       // 1-D Chebyshev nodes of the first kind
+};
+
+// Device workspace carved into typed pieces (see carve()).
+struct Work {
+  void* W = nullptr;            // weights, one slot per (A,B) pair: [P][r][nrhs] complex
+  uint32_t* keys = nullptr;     // leaf key per input point
+  uint32_t* keys_sorted = nullptr;
+  int32_t* idx = nullptr;       // 0..n-1
+  int32_t* perm = nullptr;      // input points sorted by leaf (stable)
+  int32_t* offs = nullptr;      // CSR offsets per leaf, P + 1
+  void* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+};
+
+// Optional per-step timing (bfly_timing_enable): a scope records a HIP
+// event pair around the launches it encloses when timing is on.
+enum StepKind { kStepBin = 0, kStepInit, kStepSrc, kStepSwitch, kStepTgt, kStepFinal, kNumSteps };
+class StepTimer {
+ public:
+  StepTimer(int kind, hipStream_t s);
+  ~StepTimer();
+  StepTimer(const StepTimer&) = delete;
+  StepTimer& operator=(const StepTimer&) = delete;
+
+ private:
+  int kind_;
+  hipStream_t s_;
+  hipEvent_t b_ = nullptr;
+};
+bool timing_on();
+hipError_t timing_read(double* ms, int64_t* launches);
+void timing_set(bool on);
+
+// Bytes of weight storage for one apply.
+size_t weight_bytes(const Geo& g, int nrhs, int prec);
+// Bytes of scratch the device radix sort needs for n keys of `bits` bits.
+hipError_t sort_storage_bytes(int64_t n, int bits, size_t* bytes);
+
+// Enqueue one apply (binning, initialisation, stages, switch, final
+// evaluation) on `stream`.  Inputs were validated by the caller.
+hipError_t run_apply(const Geo& g, int prec, int64_t n_in, const double* pts_in,
+                     const double* vals_in, int64_t ld_in, int64_t n_out,
+                     const double* pts_out, double* vals_out, int64_t ld_out, int nrhs,
+                     const Work& w, hipStream_t stream);
+
+}  // namespace bfly

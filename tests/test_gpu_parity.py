@@ -1,0 +1,219 @@
+"""GPU parity: the HIP butterfly (through the C ABI) against the CPU oracle.
+
+Bars: FP64 mode within 1e-12 relative (L2 over all targets and right-hand
+sides) of the oracle's FP64 butterfly at the same q; FP32 mode within 1e-5.
+Cases span several merge-and-split groups per workgroup, ragged tails of the
+last workgroup, every phase, d = 1, 2, 3, N = 1 and N = 2, empty and
+clustered inputs, several right-hand sides and the adjoint.
+"""
+import numpy as np
+import pytest
+
+from paper_1305_4650_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def gpu_run(torch, w, prec="fp64", adjoint=False, vals=None):
+    import paper_1305_4650_amd as P
+    plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+    y = torch.from_numpy(np.ascontiguousarray(w.y)).cuda()
+    x = torch.from_numpy(np.ascontiguousarray(w.x)).cuda()
+    if adjoint:
+        f = torch.from_numpy(np.ascontiguousarray(vals)).cuda()
+        out = plan.apply_adjoint(x, f, y, prec)
+    else:
+        g = torch.from_numpy(np.ascontiguousarray(w.g if vals is None else vals)).cuda()
+        out = plan.apply(y, g, x, prec)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def oracle_run(orc, w, adjoint=False, vals=None):
+    if adjoint:
+        return orc.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, w.x, vals, w.y, adjoint=True)
+    return orc.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, w.y, w.g if vals is None else vals, w.x)
+
+
+SMALL = {
+    "fourier1d_N64_q8": lambda: W.fourier_grid(64, d=1, q=8),
+    "fourier2d_N16_q5": lambda: W.fourier_grid(16, d=2, q=5),
+    "C1_fourier2d_N64_q5": lambda: W.C1(),
+    "fourier3d_N8_q3": lambda: W.fourier_grid(8, d=3, q=3),
+    "hypradon2_N2_q5": lambda: W.hypradon2(2, q=5),
+    "hypradon2_N32_q5": lambda: W.hypradon2(32, q=5),
+    "hypradon2_N64_q3_3rhs": lambda: W.hypradon2(64, q=3, nrhs=3),
+    "hypradon2_N128_q5": lambda: W.hypradon2(128, q=5),
+    "genradon3_N8_q4": lambda: W.genradon3(8, q=4),
+    "genradon3_N16_q4_2rhs": lambda: W.genradon3(16, q=4, nrhs=2),
+    "separable2d_N16_q3": lambda: W.separable(16, d=2, q=3),
+    "separable3d_N1_q2": lambda: W.separable(1, d=3, q=2),
+    "fourier2d_N1_q7": lambda: W.fourier_grid(1, d=2, q=7),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_fp64_forward_parity(torch_dev, orc, name):
+    w = SMALL[name]()
+    print(f"[case] fp64 forward {name}", flush=True)
+    f_gpu = gpu_run(torch_dev, w, "fp64")
+    f_orc = oracle_run(orc, w)
+    e = rel(f_gpu, f_orc)
+    print(f"  rel err {e:.3e}", flush=True)
+    assert e < FP64_TOL
+
+
+@pytest.mark.parametrize("name", ["fourier1d_N64_q8", "C1_fourier2d_N64_q5", "hypradon2_N32_q5",
+                                  "hypradon2_N64_q3_3rhs", "genradon3_N8_q4", "separable2d_N16_q3"])
+def test_fp64_adjoint_parity(torch_dev, orc, name):
+    w = SMALL[name]()
+    print(f"[case] fp64 adjoint {name}", flush=True)
+    vals = W.random_rhs(W.rng(w.config_id, 2), w.nrhs, w.x.shape[0])
+    g_gpu = gpu_run(torch_dev, w, "fp64", adjoint=True, vals=vals)
+    g_orc = oracle_run(orc, w, adjoint=True, vals=vals)
+    e = rel(g_gpu, g_orc)
+    print(f"  rel err {e:.3e}", flush=True)
+    assert e < FP64_TOL
+
+
+@pytest.mark.parametrize("name", ["C1_fourier2d_N64_q5", "hypradon2_N128_q5", "genradon3_N16_q4_2rhs",
+                                  "fourier1d_N64_q8"])
+def test_fp32_forward_parity(torch_dev, orc, name):
+    w = SMALL[name]()
+    print(f"[case] fp32 forward {name}", flush=True)
+    f_gpu = gpu_run(torch_dev, w, "fp32")
+    f_orc = oracle_run(orc, w)
+    e = rel(f_gpu, f_orc)
+    print(f"  rel err {e:.3e}", flush=True)
+    assert e < FP32_TOL
+
+
+def test_fp32_adjoint_parity(torch_dev, orc):
+    w = W.hypradon2(64, q=5)
+    print("[case] fp32 adjoint hypradon2_N64_q5", flush=True)
+    vals = W.random_rhs(W.rng(w.config_id, 2), 1, w.x.shape[0])
+    e = rel(gpu_run(torch_dev, w, "fp32", adjoint=True, vals=vals), oracle_run(orc, w, adjoint=True, vals=vals))
+    print(f"  rel err {e:.3e}", flush=True)
+    assert e < FP32_TOL
+
+
+def test_empty_and_uneven_inputs(torch_dev, orc):
+    """No sources; then sources clustered into few leaves, points outside the
+    boxes (clamped) and a strided right-hand-side layout."""
+    import paper_1305_4650_amd as P
+    torch = torch_dev
+    print("[case] empty / uneven inputs", flush=True)
+    w = W.hypradon2(16, q=4)
+    plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+    x = torch.from_numpy(w.x).cuda()
+    y0 = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
+    g0 = torch.zeros((1, 0), dtype=torch.complex128, device="cuda")
+    f0 = plan.apply(y0, g0, x)
+    torch.cuda.synchronize()
+    assert torch.all(f0 == 0)
+
+    # clustered sources (many per leaf, many empty leaves), strided g rows
+    gen = W.rng(42, 0)
+    ys = w.src_lo + gen.random((300, 2)) ** 3 * (w.src_hi - w.src_lo)
+    xs = w.tgt_lo + gen.random((77, 2)) * (w.tgt_hi - w.tgt_lo)
+    gs = W.random_rhs(gen, 2, ys.shape[0])
+    big = np.zeros((2, ys.shape[0] + 5), complex)
+    big[:, :ys.shape[0]] = gs
+    gt = torch.from_numpy(big).cuda()[:, :ys.shape[0]]
+    f = plan.apply(torch.from_numpy(ys).cuda(), gt, torch.from_numpy(xs).cuda())
+    torch.cuda.synchronize()
+    ref = orc.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, ys, gs, xs)
+    assert rel(f.cpu().numpy(), ref) < FP64_TOL
+
+    # points outside the boxes are clamped into the nearest leaf and the
+    # Lagrange basis is then evaluated outside [-1, 1]: its values grow like
+    # the Chebyshev polynomials there (|T_q(3)| ~ 5e2 for q = 4, per
+    # dimension), which multiplies rounding differences by ~1e5 in 2-D
+    yo = np.concatenate([ys, np.array([[0.5, -1.0], [2.5, 0.5], [2.0, 1.0]])])
+    xo = np.concatenate([xs, np.array([[1.2, -0.1], [1.0, 1.0]])])
+    go = W.random_rhs(gen, 1, yo.shape[0])
+    fo = plan.apply(torch.from_numpy(yo).cuda(), torch.from_numpy(go).cuda(), torch.from_numpy(xo).cuda())
+    torch.cuda.synchronize()
+    fo = fo.cpu().numpy()
+    ref = orc.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, yo, go, xo)
+    assert np.all(np.isfinite(fo))
+    assert rel(fo, ref) < 1e-12 * 1e5
+
+
+def test_repeatable_bitwise(torch_dev):
+    """Same inputs, same bits: no atomics in any accumulation."""
+    w = W.hypradon2(64, q=5)
+    print("[case] bitwise repeatability", flush=True)
+    a = gpu_run(torch_dev, w, "fp64")
+    b = gpu_run(torch_dev, w, "fp64")
+    assert np.array_equal(a, b)
+
+
+def test_workspace_too_small_is_reported(torch_dev):
+    import paper_1305_4650_amd as P
+    torch = torch_dev
+    w = W.hypradon2(8, q=3)
+    plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+    y = torch.from_numpy(w.y).cuda()
+    x = torch.from_numpy(w.x).cuda()
+    g = torch.from_numpy(w.g).cuda()
+    need = plan.workspace_size(w.y.shape[0], 1, "fp64")
+    ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.BflyError) as ei:
+        plan.apply(y, g, x, "fp64", workspace=ws)
+    assert ei.value.code == 5
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c2_oracle(orc):
+    w = W.C2()
+    print("[case] oracle C2 (full size)", flush=True)
+    return w, oracle_run(orc, w)
+
+
+def test_C2_full_fp64_parity(torch_dev, c2_oracle):
+    w, ref = c2_oracle
+    print("[case] fp64 forward C2 full", flush=True)
+    e = rel(gpu_run(torch_dev, w, "fp64"), ref)
+    print(f"  rel err {e:.3e}", flush=True)
+    assert e < FP64_TOL
+
+
+def test_C2_full_fp32_parity(torch_dev, c2_oracle):
+    w, ref = c2_oracle
+    print("[case] fp32 forward C2 full", flush=True)
+    e = rel(gpu_run(torch_dev, w, "fp32"), ref)
+    print(f"  rel err {e:.3e}", flush=True)
+    assert e < FP32_TOL
+
+
+def test_C2_gap_to_direct_sum(torch_dev, orc, c2_oracle):
+    """GPU vs the direct sum on sampled targets: within the oracle's own
+    butterfly error eps_q plus 1e-12."""
+    w, ref = c2_oracle
+    idx = W.sample_indices(w.x.shape[0], 128, w.config_id)
+    fd = orc.direct(w.phase, w.N, w.y, w.g, w.x[idx])
+    f = gpu_run(torch_dev, w, "fp64")
+    eps_q = rel(ref[:, idx], fd)
+    e = rel(f[:, idx], fd)
+    print(f"  gap gpu {e:.3e} oracle {eps_q:.3e}", flush=True)
+    assert e <= eps_q + 1e-12
