@@ -88,7 +88,7 @@ enum { BFLY_FP64 = 0, BFLY_FP32 = 1 };
  *  tgt_lo/tgt_hi  host double[d]: target box X
  *  phase_id one of BFLY_PHASE_*, valid for d
  *  q        Chebyshev nodes per dimension (rank r = q^d):
- *           d = 1: 2..16, d = 2: 2..16, d = 3: 2..6
+ *           d = 1: 2..16, d = 2: 2..12, d = 3: 2..5
  *  out      receives the plan (host object; no device memory, no HIP call)
  * Returns BFLY_OK, BFLY_EINVAL, BFLY_EUNSUPPORTED or BFLY_ENOMEM. */
 int bfly_plan(int d, int64_t N, const double* src_lo, const double* src_hi,

@@ -13,7 +13,8 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbfly.so")
+# BFLY_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("BFLY_LIBRARY") or os.path.join(HERE, "libbfly.so")
 
 BFLY_OK, BFLY_EINVAL, BFLY_EUNSUPPORTED, BFLY_ENOMEM, BFLY_EDEVICE, BFLY_EWORKSPACE = range(6)
 BFLY_PHASE_FOURIER, BFLY_PHASE_HYPRADON2, BFLY_PHASE_GENRADON3, BFLY_PHASE_SEPARABLE_TEST = range(4)

@@ -30,34 +30,34 @@ COMMON = [
     "-I", os.path.join(ROOT, "include"),
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
-SOURCES = ["bfly_kernels.hip", "bfly_api.cpp", "bfly_timing.cpp"]
+SOURCES = ["bfly_d2.hip", "bfly_d3.hip", "bfly_d1.hip", "bfly_common.hip", "bfly_api.cpp", "bfly_timing.cpp"]
 
 
-def build(verbose: bool = True, jobs: int = 4) -> str:
-    """Compile every source (always) and link libbfly.so."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = True, jobs: int = 6, out: str = LIB, defines=(), build_dir: str = BUILD) -> str:
+    """Compile every source (always) and link libbfly.so (or `out`)."""
+    os.makedirs(build_dir, exist_ok=True)
     t0 = time.time()
     procs = []
     objs = []
     for src in SOURCES:
-        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *COMMON, *[f"-D{d}" for d in defines], "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd)))
         if len(procs) >= jobs:
             _wait(procs)
     _wait(procs)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {LIB} in {time.time() - t0:.1f}s", flush=True)
-    return LIB
+        print(f"built {out} in {time.time() - t0:.1f}s", flush=True)
+    return out
 
 
 def _wait(procs):

@@ -42,7 +42,7 @@ int ok() {
   return BFLY_OK;
 }
 
-int q_max(int d) { return d == 3 ? 6 : 16; }
+int q_max(int d) { return d == 1 ? 16 : (d == 2 ? 12 : 5); }
 
 constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }

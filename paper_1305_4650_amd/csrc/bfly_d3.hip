@@ -1,0 +1,35 @@
+// Fused level kernels for d = 3: one instantiation per supported q and
+// precision (and a phase-specialised one for the benchmark workloads).
+#include "bfly_fused.inc"
+
+namespace bfly {
+namespace {
+
+template <int Q>
+hipError_t run_q(const LevelArgs& la, int prec) {
+  const int ph = la.G->phase;
+  (void)ph;
+  if constexpr (Q == 4) {
+    if (ph == 2) return prec == 0 ? fz::run_levels_t<3, Q, double, 2>(la) : fz::run_levels_t<3, Q, float, 2>(la);
+  }
+  return prec == 0 ? fz::run_levels_t<3, Q, double, -1>(la) : fz::run_levels_t<3, Q, float, -1>(la);
+}
+
+}  // namespace
+
+hipError_t run_levels_d3(const LevelArgs& la, int prec) {
+  switch (la.G->q) {
+    case 2:
+      return run_q<2>(la, prec);
+    case 3:
+      return run_q<3>(la, prec);
+    case 4:
+      return run_q<4>(la, prec);
+    case 5:
+      return run_q<5>(la, prec);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace bfly

@@ -1,5 +1,14 @@
 // Internal declarations shared by the host API and the kernel launchers of
 // libbfly.  Not installed; the public interface is include/bfly.h.
+//
+// Weight layout (in place across all levels).  The N^d (A,B) pairs of every
+// level live in N^d slots of r * nrhs complex values ([slot][node][rhs]).
+// Viewing a slot index as L digits of d bits, at level l the low l digits
+// hold the target box A (digit k = the bits of A's (k+1)-th split, coarsest
+// first) and the high L - l digits hold the source box B in Morton order
+// (finest digit lowest).  Stage l merges the 2^d source children (digit l)
+// and splits the target into 2^d children, which land in the same digit:
+// each merge-and-split group reads and writes the same 2^d slots.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -59,6 +68,29 @@ void timing_set(bool on);
 size_t weight_bytes(const Geo& g, int nrhs, int prec);
 // Bytes of scratch the device radix sort needs for n keys of `bits` bits.
 hipError_t sort_storage_bytes(int64_t n, int bits, size_t* bytes);
+
+// Everything the level kernels of one apply need (after binning).
+struct LevelArgs {
+  const Geo* G = nullptr;
+  void* W = nullptr;             // weights (FP64 or FP32 complex)
+  int nrhs = 1;
+  const double* pts_in = nullptr;
+  const double* vals_in = nullptr;
+  int64_t ld_in = 0;
+  const int32_t* perm = nullptr;
+  const int32_t* offs = nullptr;
+  int64_t n_out = 0;
+  const double* pts_out = nullptr;
+  double* vals_out = nullptr;
+  int64_t ld_out = 0;
+  hipStream_t stream = nullptr;
+  int vb_target = 16;            // weight vectors per workgroup block
+  int k_fuse = 2;                // merge-and-split stages fused per launch (at most)
+  size_t lds_budget = 81920;     // bytes of LDS per workgroup (two workgroups per CU)
+};
+hipError_t run_levels_d1(const LevelArgs& la, int prec);
+hipError_t run_levels_d2(const LevelArgs& la, int prec);
+hipError_t run_levels_d3(const LevelArgs& la, int prec);
 
 // Enqueue one apply (binning, initialisation, stages, switch, final
 // evaluation) on `stream`.  Inputs were validated by the caller.
