@@ -23,6 +23,8 @@ import time
 import numpy as np
 
 METRIC = "Mpoints/s per butterfly apply (2D N=1024, q=5); FP32-MFMA vs FP64 at 1e-5 rel err"
+ROOT = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(ROOT, "paper_1305_4650_amd", "csrc")
 PEAK_VALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, non-packed VALU issue rate
 
 # Flops charged per evaluation of tau (sqrt, sin and cos as below), see the design doc.
@@ -36,30 +38,66 @@ def phase_flops(phase: str, d: int) -> int:
     return TAU_FLOPS[phase](d) + 2 + SINCOS_FLOPS
 
 
-def algorithmic_flops(step: str, phase: str, d: int, N: int, q: int, nrhs: int, n_src: int, n_tgt: int):
-    """Algorithmic flops of ONE launch of a step (tensor-factored contraction
-    counts, phase evaluations at a fixed cost, complex multiply = 6 flops,
-    real x complex multiply-add = 4 flops)."""
+def stage_flops(kind: str, phase: str, d: int, N: int, q: int, nrhs: int) -> float:
+    """Algorithmic flops of one merge-and-split stage over all N^d pairs.
+    Column space (first half): per output vector (2^d + 1) r phase factors
+    and (2^(d+1) - 2) q^(d+1) real x complex multiply-adds (tensor form);
+    row space (second half): the same phase count and 2^d d q^(d+1)."""
     r, nc, P = q ** d, 2 ** d, N ** d
-    cphi = phase_flops(phase, d)
-    if step == "stage_src":
-        evals = P * (nc + 1) * r
-        macs = P * (2 ** (d + 1) - 2) * q ** (d + 1)
-        return evals * cphi + evals * nrhs * 6 + macs * nrhs * 4
-    if step == "stage_tgt":
-        evals = P * (nc + 1) * r
-        macs = P * nc * d * q ** (d + 1)
-        return evals * cphi + evals * nrhs * 6 + macs * nrhs * 4
-    if step == "switch":
-        evals = P * r * r
-        return evals * cphi + evals * nrhs * 8
-    if step == "init":
-        evals = n_src + P * r
-        return evals * cphi + evals * nrhs * 6 + n_src * r * nrhs * 4
-    if step == "final":
-        evals = n_tgt + P * r
-        return evals * cphi + evals * nrhs * 6 + n_tgt * r * nrhs * 4
-    return 0
+    evals = P * (nc + 1) * r
+    macs = P * ((2 ** (d + 1) - 2) if kind == "first" else nc * d) * q ** (d + 1)
+    return evals * phase_flops(phase, d) + evals * nrhs * 6 + macs * nrhs * 4
+
+
+def init_flops(phase, d, N, q, nrhs, n_src):
+    r, P = q ** d, N ** d
+    evals = n_src + P * r
+    return evals * phase_flops(phase, d) + evals * nrhs * 6 + n_src * r * nrhs * 4
+
+
+def switch_flops(phase, d, N, q, nrhs):
+    r, P = q ** d, N ** d
+    evals = P * r * r
+    return evals * phase_flops(phase, d) + evals * nrhs * 8
+
+
+def final_flops(phase, d, N, q, nrhs, n_tgt):
+    r, P = q ** d, N ** d
+    evals = n_tgt + P * r
+    return evals * phase_flops(phase, d) + evals * nrhs * 6 + n_tgt * r * nrhs * 4
+
+
+def kind_flops(kind: str, t: dict, w, n_src: int, n_tgt: int) -> float:
+    """Algorithmic flops of all launches of one kind, from the work counts
+    the library reports for them."""
+    a = (w.phase, w.d, w.N, w.q, w.nrhs)
+    if kind == "first":
+        return (t["stages"] * stage_flops("first", *a) + t["inits"] * init_flops(*a, n_src)
+                + t["switches"] * switch_flops(*a))
+    if kind == "second":
+        return t["stages"] * stage_flops("second", *a)
+    if kind == "final":
+        return t["launches"] * final_flops(*a, n_tgt)
+    return 0.0
+
+
+def traffic_per_launch(kernel_family: str):
+    """HBM bytes per launch of a kernel family from the committed counter
+    summary, or None if the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    if rec.get("source_sha256") != h.hexdigest():
+        return None
+    fam = rec.get("kernels", {}).get(kernel_family)
+    return None if fam is None else fam.get("hbm_bytes_per_launch")
 
 
 def rel(a, b):
@@ -88,7 +126,18 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (no rel err either)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (default: all in affinity)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run one plain device copy of 1 GiB (scales the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4}))
+        return 0
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
               "the apply does not shard across GPUs.", file=sys.stderr)
@@ -130,8 +179,8 @@ def main() -> int:
         P.bfly_timing_enable(False)
         res[prec] = {"ms": ms, "out": f.cpu().numpy(), "timing": tim}
         print(f"[bench] {prec}: {ms:.3f} ms/apply  {npts / ms / 1e3:.1f} Mpoints/s  "
-              + " ".join(f"{k}={v[0] / max(v[1], 1):.3f}ms" for k, v in tim.items()),
-              file=sys.stderr, flush=True)
+              + " ".join(f"{k}={v['ms'] / args.steps:.3f}ms/{v['launches'] // args.steps}"
+                         for k, v in tim.items()), file=sys.stderr, flush=True)
         del ws
 
     cpu = None
@@ -151,14 +200,21 @@ def main() -> int:
 
     head = "fp32"
     tim = res[head]["timing"]
-    dom = max(tim, key=lambda k: tim[k][0])
-    launches = max(tim[dom][1], 1)
-    avg_ms = tim[dom][0] / launches
-    flops = algorithmic_flops(dom, w.phase, w.d, w.N, w.q, w.nrhs, n, w.x.shape[0])
+    dom = max(tim, key=lambda k: tim[k]["ms"])
+    launches = max(tim[dom]["launches"], 1)
+    avg_ms = tim[dom]["ms"] / launches
+    flops = kind_flops(dom, tim[dom], w, n, w.x.shape[0]) / launches
     achieved = flops / (avg_ms * 1e-3) / 1e12
+    fam = {"first": "k_first", "second": "k_second", "final": "k_final"}.get(dom, dom)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_VALU_TFLOPS, 4), "traffic": None, "kernel": dom,
-                "avg_launch_ms": round(avg_ms, 5), "algorithmic_flops_per_launch": flops}
+                "frac": round(achieved / PEAK_VALU_TFLOPS, 4), "traffic": traffic_per_launch(fam),
+                "kernel": fam, "avg_launch_ms": round(avg_ms, 5),
+                "algorithmic_flops_per_launch": round(flops)}
+    total_flops = sum(kind_flops(k, tim[k], w, n, w.x.shape[0]) for k in tim)
+    total_s = sum(t["ms"] for t in tim.values()) * 1e-3
+    apply_roofline = {"achieved": round(total_flops / total_s / 1e12, 3),
+                      "frac": round(total_flops / total_s / 1e12 / PEAK_VALU_TFLOPS, 4),
+                      "algorithmic_flops_per_apply": round(total_flops / args.steps)}
     out = {
         "metric": METRIC,
         "value": round(npts / res[head]["ms"] / 1e3, 3),
@@ -181,8 +237,9 @@ def main() -> int:
         "fp64": {"value": round(npts / res["fp64"]["ms"] / 1e3, 3), "ms_per_step": round(res["fp64"]["ms"], 4),
                  "rel_err_vs_oracle": res["fp64"].get("rel_err")},
         "speedup_fp32_over_fp64": round(res["fp64"]["ms"] / res[head]["ms"], 3),
-        "step_ms": {p: {k: round(v[0] / max(v[1], 1), 5) for k, v in res[p]["timing"].items()} for p in res},
+        "launch_ms": {p: {k: round(v["ms"] / args.steps, 5) for k, v in res[p]["timing"].items()} for p in res},
         "roofline": roofline,
+        "apply_roofline_fp32": apply_roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

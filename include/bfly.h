@@ -3,8 +3,8 @@
  *
  * The library applies the butterfly algorithm of Poulson, Demanet, Maxwell &
  * Ying, "A Parallel Butterfly Algorithm", to kernels K(x, y) = exp(i Phi(x, y))
- * with a smooth real phase Phi (Sec. 2, Eq. "phase"), using analytic
- * tensor-product Chebyshev interpolation (Sec. 2 "Avoiding quadratic
+ * with a smooth real phase Phi (Sec. 1.4, Eq. (6)), using analytic
+ * tensor-product Chebyshev interpolation (Sec. 1.4 "Avoiding quadratic
  * precomputation"):
  *
  *   f(x) ~= sum_y exp(i Phi(x, y)) g(y)            (Sec. 1, Eq. 1 over all boxes)
@@ -61,11 +61,11 @@ enum {
 };
 
 /* phase ids (tau = Phi / 2 pi; N is the plan's N)
- *  FOURIER      tau = x . y                                  any d  (Sec. 4)
- *  HYPRADON2    tau = N x0 sqrt(y0^2 + x1^2 y1^2)            d = 2  (Sec. 4.1 family)
+ *  FOURIER      tau = x . y                                  any d  (Sec. 3)
+ *  HYPRADON2    tau = N x0 sqrt(y0^2 + x1^2 y1^2)            d = 2  (Sec. 3.1 family)
  *  GENRADON3    tau = N (x.y + sqrt(g0^2 y0^2 + g1^2 y1^2 + y2^2)),
  *               g0 = (2 + sin 2pi x0 sin 2pi x1)/3,
- *               g1 = (2 + cos 2pi x0 cos 2pi x1)/3           d = 3  (Sec. 4.2 family)
+ *               g1 = (2 + cos 2pi x0 cos 2pi x1)/3           d = 3  (Sec. 3.2 family)
  *  SEPARABLE_TEST tau = N (sum_j x_j^2 + sum_j y_j^3)        any d  (rank-one kernel:
  *               the butterfly is exact, used to check results at any size) */
 enum {
@@ -76,7 +76,7 @@ enum {
 };
 
 /* precision modes (internal arithmetic; I/O is always complex128)
- *  FP64   everything in FP64 (the paper computes in double precision, Sec. 4).
+ *  FP64   everything in FP64 (the paper computes in double precision, Sec. 3).
  *  FP32   phase tau and its reduction modulo 1 in FP64, then FP32
  *         sine/cosine, FP32 weights and FP32 contractions. */
 enum { BFLY_FP64 = 0, BFLY_FP32 = 1 };
@@ -144,18 +144,21 @@ int bfly_apply_adjoint(bfly_plan_t plan,
 
 /* Per-step timing, for profiling.  While enabled, every apply records a HIP
  * event pair around each kernel launch on its stream (a few microseconds of
- * overhead per launch).  bfly_timing_read waits for the recorded events,
- * writes the accumulated milliseconds and launch counts per step kind since
- * the previous read, and resets them.  Step kinds (BFLY_STEP_*):
- *   0 binning (leaf keys, sort, CSR offsets)   1 initialisation
- *   2 first-half stages                         3 middle switch
- *   4 second-half stages                        5 final evaluation
- * ms and launches are host arrays of BFLY_NUM_STEPS entries.  The timing
+ * overhead per launch).  bfly_timing_read waits for the recorded events and
+ * writes, per launch kind, the accumulated milliseconds, the number of
+ * launches and the work those launches performed (merge-and-split stages,
+ * leaf initialisations, middle switches) since the previous read, then
+ * resets the counts.  Launch kinds (BFLY_STEP_*):
+ *   0 binning (leaf keys, sort, CSR offsets)
+ *   1 column-space launches: leaf initialisation, first-half stages, switch
+ *   2 row-space launches: second-half stages
+ *   3 final evaluation
+ * All five arrays are host arrays of BFLY_NUM_STEPS entries.  The timing
  * state is process-wide; do not enable it while several threads apply.
  * Returns BFLY_OK, BFLY_EINVAL or BFLY_EDEVICE. */
-enum { BFLY_NUM_STEPS = 6 };
+enum { BFLY_NUM_STEPS = 4 };
 int bfly_timing_enable(int on);
-int bfly_timing_read(double* ms, int64_t* launches);
+int bfly_timing_read(double* ms, int64_t* launches, int64_t* stages, int64_t* inits, int64_t* switches);
 
 /* Static description of a status code. */
 const char* bfly_status_string(int status);

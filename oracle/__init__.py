@@ -3,7 +3,7 @@
 Plain FP64 reference implementations of the direct sum (Eq. 1 of Poulson,
 Demanet, Maxwell & Ying, "A Parallel Butterfly Algorithm") and of the
 sequential butterfly algorithm (Alg. "alg:serial") with analytic Chebyshev
-interpolation (Sec. 2, "Avoiding quadratic precomputation").  The arithmetic
+interpolation (Sec. 1.4, "Avoiding quadratic precomputation").  The arithmetic
 lives in ``bfly_oracle.c``; this module only builds, loads and marshals.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of

@@ -3,15 +3,15 @@
  *
  * A plain FP64 CPU implementation of
  *   (1) the direct sum f(x) = sum_y exp(i Phi(x,y)) g(y)        (Sec. 1, Eq. 1), and
- *   (2) the butterfly apply of Alg. "alg:serial" (Sec. 2) with the analytic
+ *   (2) the butterfly apply of Alg. "alg:serial" (Sec. 1.3) with the analytic
  *       tensor-product Chebyshev translation operators the paper runs for
- *       K = exp(i Phi) (Sec. 2 "Avoiding quadratic precomputation"):
+ *       K = exp(i Phi) (Sec. 1.4 "Avoiding quadratic precomputation"):
  *       column-space (source) interpolation while the source boxes are small,
  *       the middle switch, then row-space (target) interpolation.
  *
  * The paper cites the translation operators rather than printing them; the
  * formulas used here are derived from its definitions of potentials and
- * expansion weights (Sec. 1) and of equivalent sources (Sec. 2), with the
+ * expansion weights (Sec. 1) and of equivalent sources (Sec. 1.2), with the
  * readings recorded at the top of each step.  Translations are applied in
  * DENSE form (an r x 2^d r real matrix between two phase diagonals), which
  * shares nothing with the tensor-factored GPU kernels.
@@ -46,18 +46,18 @@ static inline cplx cmul(cplx a, cplx b) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Phase functions (the kernel K = exp(2 pi i tau), Eq. "phase").             */
+/* Phase functions (the kernel K = exp(2 pi i tau), Eq. (6)).             */
 /* ------------------------------------------------------------------------ */
 
 double orc_tau(int phase, int d, long N, const double* x, const double* y) {
   const double Nd = (double)N;
   switch (phase) {
-    case ORC_FOURIER: { /* Phi = 2 pi x.y (Sec. 4, list of kernels) */
+    case ORC_FOURIER: { /* Phi = 2 pi x.y (Sec. 3, list of kernels) */
       double s = x[0] * y[0];
       for (int j = 1; j < d; ++j) s = s + x[j] * y[j];
       return s;
     }
-    case ORC_HYPRADON2: { /* hyperbolic Radon family (Sec. 4.1), roles as in the workload */
+    case ORC_HYPRADON2: { /* hyperbolic Radon family (Sec. 3.1), roles as in the workload */
       double a = y[0] * y[0];
       double b = x[1] * x[1];
       double c = y[1] * y[1];
@@ -66,7 +66,7 @@ double orc_tau(int phase, int d, long N, const double* x, const double* y) {
       double m = Nd * x[0];
       return m * sqrt(s);
     }
-    case ORC_GENRADON3: { /* generalized-Radon analogue (Sec. 4.2), workload form */
+    case ORC_GENRADON3: { /* generalized-Radon analogue (Sec. 3.2), workload form */
       double u0 = TWO_PI * x[0];
       double u1 = TWO_PI * x[1];
       double g0 = (2.0 + sin(u0) * sin(u1)) / 3.0;
@@ -395,7 +395,7 @@ int orc_butterfly(int d, long N, int q, int phase,
    *   delta^{A'B'}_t = e^{-i Phi(c_A', y^{B'}_t)} sum_c sum_t2 L^{B'}_t(y^{B_c}_t2)
    *                    e^{i Phi(c_A', y^{B_c}_t2)} delta^{P B_c}_t2,
    * i.e. the step-2 formula applied to the children's equivalent sources
-   * (Sec. 2 "Translating equivalent sources"). */
+   * (Sec. 1.3 "Translating equivalent sources"). */
   for (int l = 0; l < p->ls; ++l) {
     const int lb_out = L - l - 1; /* source bits per dim at level l+1 */
 #pragma omp parallel for schedule(dynamic, 64) num_threads(nt) reduction(+ : n_phase, n_mac)
@@ -444,7 +444,7 @@ int orc_butterfly(int d, long N, int q, int phase,
     Wn = tmp;
   }
 
-  /* ---- 4. middle switch at level ls (Sec. 2): equivalent sources at the
+  /* ---- 4. middle switch at level ls (Sec. 1.4): equivalent sources at the
    * nodes of B become potentials at the nodes of A,
    *   delta^{AB}_t <- sum_s e^{i Phi(x^A_t, y^B_s)} delta^{AB}_s. */
   {
@@ -482,7 +482,7 @@ int orc_butterfly(int d, long N, int q, int phase,
   }
 
   /* ---- 5. second half: stages l = ls .. L-1, row-space interpolation
-   * (Sec. 2).  Weights are now potentials at the nodes of the target box.
+   * (Sec. 1.3-1.4).  Weights are now potentials at the nodes of the target box.
    * Interpolating x -> exp(i(Phi(x,y) - Phi(x,c_B))) on the parent's nodes:
    *   delta^{A'B'}_t = sum_c e^{i Phi(x^{A'}_t, c_{B_c})} sum_t2 L^P_t2(x^{A'}_t)
    *                    e^{-i Phi(x^P_t2, c_{B_c})} delta^{P B_c}_t2. */

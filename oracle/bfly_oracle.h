@@ -4,7 +4,7 @@
  * Plain, slow, FP64 CPU reference for the butterfly apply of Poulson, Demanet,
  * Maxwell & Ying, "A Parallel Butterfly Algorithm" (sequential algorithm,
  * Alg. "alg:serial", with the analytic Chebyshev translation operators of
- * Sec. 2 "Avoiding quadratic precomputation"), and for the direct sum it
+ * Sec. 1.4 "Avoiding quadratic precomputation"), and for the direct sum it
  * approximates (Eq. 1).  Only tests, the smoke check and the CPU-baseline leg
  * of the benchmark may call this library.  It shares no code with the GPU
  * library.

@@ -2,7 +2,7 @@
 
 Implements the butterfly algorithm of Poulson, Demanet, Maxwell & Ying, "A
 Parallel Butterfly Algorithm" (sequential form, Alg. "alg:serial", with the
-analytic Chebyshev interpolation of Sec. 2) as HIP kernels for gfx950 behind
+analytic Chebyshev interpolation of Sec. 1.4) as HIP kernels for gfx950 behind
 the C ABI of include/bfly.h.  This package is the Python binding
 (``bfly.py``), the build script (``build.py``) and the seeded synthetic
 workloads (``workloads.py``).

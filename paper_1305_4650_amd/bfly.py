@@ -26,7 +26,7 @@ PRECISIONS = {"fp64": BFLY_FP64, "fp32": BFLY_FP32}
 EXPORTS = ("bfly_plan", "bfly_plan_destroy", "bfly_plan_info", "bfly_workspace_size", "bfly_apply",
            "bfly_apply_adjoint", "bfly_timing_enable", "bfly_timing_read", "bfly_status_string",
            "bfly_last_error")
-STEP_NAMES = ("binning", "init", "stage_src", "switch", "stage_tgt", "final")
+STEP_NAMES = ("binning", "first", "second", "final")
 
 
 class BflyError(RuntimeError):
@@ -64,7 +64,7 @@ def lib() -> ctypes.CDLL:
     L.bfly_timing_enable.restype = ctypes.c_int
     L.bfly_timing_enable.argtypes = [ctypes.c_int]
     L.bfly_timing_read.restype = ctypes.c_int
-    L.bfly_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    L.bfly_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double)] + [ctypes.POINTER(i64)] * 4
     L.bfly_status_string.restype = ctypes.c_char_p
     L.bfly_status_string.argtypes = [ctypes.c_int]
     L.bfly_last_error.restype = ctypes.c_char_p
@@ -126,11 +126,12 @@ def bfly_timing_enable(on: bool) -> None:
 
 
 def bfly_timing_read() -> dict:
-    """{step name: (milliseconds, launches)} accumulated since the last read."""
+    """{launch kind: {"ms", "launches", "stages", "inits", "switches"}} since the last read."""
     ms = (ctypes.c_double * len(STEP_NAMES))()
-    n = (ctypes.c_int64 * len(STEP_NAMES))()
-    _check(lib().bfly_timing_read(ms, n), "bfly_timing_read")
-    return {k: (ms[i], n[i]) for i, k in enumerate(STEP_NAMES)}
+    cnt = [(ctypes.c_int64 * len(STEP_NAMES))() for _ in range(4)]
+    _check(lib().bfly_timing_read(ms, *cnt), "bfly_timing_read")
+    return {k: {"ms": ms[i], "launches": cnt[0][i], "stages": cnt[1][i], "inits": cnt[2][i],
+                "switches": cnt[3][i]} for i, k in enumerate(STEP_NAMES)}
 
 
 def bfly_status_string(status: int) -> str:

@@ -199,7 +199,7 @@ int bfly_plan(int d, int64_t N, const double* src_lo, const double* src_hi, cons
     p->tgt_lo[j] = tgt_lo[j];
     p->tgt_hi[j] = tgt_hi[j];
   }
-  // Chebyshev nodes of the first kind (the grid of Sec. 2)
+  // Chebyshev nodes of the first kind (the grid of Sec. 1.4)
   for (int k = 0; k < q; ++k) p->z[k] = std::cos((double)(2 * k + 1) * M_PI / (double)(2 * q));
   *out = p;
   return ok();
@@ -250,9 +250,9 @@ int bfly_timing_enable(int on) {
   return ok();
 }
 
-int bfly_timing_read(double* ms, int64_t* launches) {
-  if (!ms || !launches) return fail(BFLY_EINVAL, "output arrays are NULL");
-  hipError_t e = bfly::timing_read(ms, launches);
+int bfly_timing_read(double* ms, int64_t* launches, int64_t* stages, int64_t* inits, int64_t* switches) {
+  if (!ms || !launches || !stages || !inits || !switches) return fail(BFLY_EINVAL, "output arrays are NULL");
+  hipError_t e = bfly::timing_read(ms, launches, stages, inits, switches);
   if (e != hipSuccess) return fail(BFLY_EDEVICE, "timing events failed: %s", hipGetErrorString(e));
   return ok();
 }

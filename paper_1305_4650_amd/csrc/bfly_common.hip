@@ -2,7 +2,7 @@
 // dispatch of one apply to the fused level kernels (bfly_fused.inc).
 //
 // Steps of one apply (Alg. "alg:serial" of Poulson, Demanet, Maxwell & Ying,
-// with the analytic Chebyshev translations of Sec. 2 "Avoiding quadratic
+// with the analytic Chebyshev translations of Sec. 1.4 "Avoiding quadratic
 // precomputation"):
 //   binning      leaf of every input point (level-0 source tree), stable sort
 //                by leaf Morton index, CSR offsets per leaf      (this file)

@@ -1,5 +1,6 @@
 // Fused level kernels for d = 1: one instantiation per supported q and
-// precision (and a phase-specialised one for the benchmark workloads).
+// precision, plus phase-specialised ones (with right-hand sides processed in
+// chunks that share their phase factors) for the benchmark workloads.
 #include "bfly_fused.inc"
 
 namespace bfly {
@@ -9,7 +10,7 @@ template <int Q>
 hipError_t run_q(const LevelArgs& la, int prec) {
   const int ph = la.G->phase;
   (void)ph;
-  return prec == 0 ? fz::run_levels_t<1, Q, double, -1>(la) : fz::run_levels_t<1, Q, float, -1>(la);
+  return prec == 0 ? fz::run_levels_t<1, Q, double, -1, 1>(la) : fz::run_levels_t<1, Q, float, -1, 1>(la);
 }
 
 }  // namespace

@@ -1,5 +1,8 @@
 // Fused level kernels for d = 2: one instantiation per supported q and
-// precision (and a phase-specialised one for the benchmark workloads).
+// precision, plus phase-specialised ones for the benchmark workloads.  The
+// expensive phases (hyperbolic and generalized Radon) process right-hand
+// sides in chunks that share their phase factors; the Fourier phase costs a
+// few flops, so chunking it only adds register pressure (measured slower).
 #include "bfly_fused.inc"
 
 namespace bfly {
@@ -10,15 +13,18 @@ hipError_t run_q(const LevelArgs& la, int prec) {
   const int ph = la.G->phase;
   (void)ph;
   if constexpr (Q == 5) {
-    if (ph == 0) return prec == 0 ? fz::run_levels_t<2, Q, double, 0>(la) : fz::run_levels_t<2, Q, float, 0>(la);
+    if (ph == 0)
+      return prec == 0 ? fz::run_levels_t<2, Q, double, 0, 1>(la) : fz::run_levels_t<2, Q, float, 0, 1>(la);
   }
   if constexpr (Q == 5) {
-    if (ph == 1) return prec == 0 ? fz::run_levels_t<2, Q, double, 1>(la) : fz::run_levels_t<2, Q, float, 1>(la);
+    if (ph == 1)
+      return prec == 0 ? fz::run_levels_t<2, Q, double, 1, BFLY_RHS_CHUNK_FP64>(la) : fz::run_levels_t<2, Q, float, 1, BFLY_RHS_CHUNK_FP32>(la);
   }
   if constexpr (Q == 6) {
-    if (ph == 0) return prec == 0 ? fz::run_levels_t<2, Q, double, 0>(la) : fz::run_levels_t<2, Q, float, 0>(la);
+    if (ph == 0)
+      return prec == 0 ? fz::run_levels_t<2, Q, double, 0, 1>(la) : fz::run_levels_t<2, Q, float, 0, 1>(la);
   }
-  return prec == 0 ? fz::run_levels_t<2, Q, double, -1>(la) : fz::run_levels_t<2, Q, float, -1>(la);
+  return prec == 0 ? fz::run_levels_t<2, Q, double, -1, 1>(la) : fz::run_levels_t<2, Q, float, -1, 1>(la);
 }
 
 }  // namespace

@@ -1,5 +1,8 @@
 // Fused level kernels for d = 3: one instantiation per supported q and
-// precision (and a phase-specialised one for the benchmark workloads).
+// precision, plus phase-specialised ones for the benchmark workloads.  The
+// expensive phases (hyperbolic and generalized Radon) process right-hand
+// sides in chunks that share their phase factors; the Fourier phase costs a
+// few flops, so chunking it only adds register pressure (measured slower).
 #include "bfly_fused.inc"
 
 namespace bfly {
@@ -10,9 +13,10 @@ hipError_t run_q(const LevelArgs& la, int prec) {
   const int ph = la.G->phase;
   (void)ph;
   if constexpr (Q == 4) {
-    if (ph == 2) return prec == 0 ? fz::run_levels_t<3, Q, double, 2>(la) : fz::run_levels_t<3, Q, float, 2>(la);
+    if (ph == 2)
+      return prec == 0 ? fz::run_levels_t<3, Q, double, 2, BFLY_RHS_CHUNK_FP64>(la) : fz::run_levels_t<3, Q, float, 2, BFLY_RHS_CHUNK_FP32>(la);
   }
-  return prec == 0 ? fz::run_levels_t<3, Q, double, -1>(la) : fz::run_levels_t<3, Q, float, -1>(la);
+  return prec == 0 ? fz::run_levels_t<3, Q, double, -1, 1>(la) : fz::run_levels_t<3, Q, float, -1, 1>(la);
 }
 
 }  // namespace

@@ -47,21 +47,22 @@ struct Work {
 
 // Optional per-step timing (bfly_timing_enable): a scope records a HIP
 // event pair around the launches it encloses when timing is on.
-enum StepKind { kStepBin = 0, kStepInit, kStepSrc, kStepSwitch, kStepTgt, kStepFinal, kNumSteps };
+enum StepKind { kStepBin = 0, kStepFirst, kStepSecond, kStepFinal, kNumSteps };
 class StepTimer {
  public:
-  StepTimer(int kind, hipStream_t s);
+  // stages / inits / switches: work the enclosed launch performs
+  StepTimer(int kind, hipStream_t s, int stages = 0, int inits = 0, int switches = 0);
   ~StepTimer();
   StepTimer(const StepTimer&) = delete;
   StepTimer& operator=(const StepTimer&) = delete;
 
  private:
-  int kind_;
+  int kind_, stages_, inits_, switches_;
   hipStream_t s_;
   hipEvent_t b_ = nullptr;
 };
 bool timing_on();
-hipError_t timing_read(double* ms, int64_t* launches);
+hipError_t timing_read(double* ms, int64_t* launches, int64_t* stages, int64_t* inits, int64_t* switches);
 void timing_set(bool on);
 
 // Bytes of weight storage for one apply.

@@ -9,7 +9,7 @@ namespace bfly {
 namespace {
 
 struct Pending {
-  int kind;
+  int kind, stages, inits, switches;
   hipEvent_t b, e;
 };
 
@@ -19,7 +19,7 @@ struct State {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   double ms[kNumSteps] = {};
-  int64_t launches[kNumSteps] = {};
+  int64_t launches[kNumSteps] = {}, stages[kNumSteps] = {}, inits[kNumSteps] = {}, switches[kNumSteps] = {};
 };
 
 State& st() {
@@ -48,7 +48,8 @@ void timing_set(bool on) {
   s.on = on;
 }
 
-StepTimer::StepTimer(int kind, hipStream_t s) : kind_(kind), s_(s) {
+StepTimer::StepTimer(int kind, hipStream_t s, int stages, int inits, int switches)
+    : kind_(kind), stages_(stages), inits_(inits), switches_(switches), s_(s) {
   State& S = st();
   if (!S.on) return;
   std::lock_guard<std::mutex> lk(S.mu);
@@ -66,10 +67,10 @@ StepTimer::~StepTimer() {
     return;
   }
   (void)hipEventRecord(e, s_);
-  S.pending.push_back({kind_, b_, e});
+  S.pending.push_back({kind_, stages_, inits_, switches_, b_, e});
 }
 
-hipError_t timing_read(double* ms, int64_t* launches) {
+hipError_t timing_read(double* ms, int64_t* launches, int64_t* stages, int64_t* inits, int64_t* switches) {
   State& S = st();
   std::lock_guard<std::mutex> lk(S.mu);
   hipError_t err = hipSuccess;
@@ -82,6 +83,9 @@ hipError_t timing_read(double* ms, int64_t* launches) {
     } else {
       S.ms[p.kind] += t;
       S.launches[p.kind] += 1;
+      S.stages[p.kind] += p.stages;
+      S.inits[p.kind] += p.inits;
+      S.switches[p.kind] += p.switches;
     }
     S.pool.push_back(p.b);
     S.pool.push_back(p.e);
@@ -90,8 +94,11 @@ hipError_t timing_read(double* ms, int64_t* launches) {
   for (int k = 0; k < kNumSteps; ++k) {
     ms[k] = S.ms[k];
     launches[k] = S.launches[k];
+    stages[k] = S.stages[k];
+    inits[k] = S.inits[k];
+    switches[k] = S.switches[k];
     S.ms[k] = 0;
-    S.launches[k] = 0;
+    S.launches[k] = S.stages[k] = S.inits[k] = S.switches[k] = 0;
   }
   return err;
 }

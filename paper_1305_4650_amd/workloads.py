@@ -5,7 +5,7 @@ the method's arithmetic -- so that the GPU path, the tests and the benchmark
 all draw identical inputs.
 
 The paper measures on synthetic quasi-uniform points with analytic phases
-(Sec. 4: a hyperbolic Radon transform and a 3-D generalized-Radon analogue,
+(Sec. 3: a hyperbolic Radon transform and a 3-D generalized-Radon analogue,
 and the Fourier kernel named in the same section); no dataset is involved.
 
 Conventions

@@ -64,6 +64,12 @@ SMALL = {
     "separable2d_N16_q3": lambda: W.separable(16, d=2, q=3),
     "separable3d_N1_q2": lambda: W.separable(1, d=3, q=2),
     "fourier2d_N1_q7": lambda: W.fourier_grid(1, d=2, q=7),
+    # right-hand sides processed in chunks (phase factors shared by a chunk)
+    # plus a remainder: the phase-specialised paths for d = 2, q = 5 / 6
+    "hypradon2_N32_q5_9rhs": lambda: W.hypradon2(32, q=5, nrhs=9),
+    "fourier2d_N32_q6_9rhs": lambda: W.fourier_grid(32, d=2, q=6, nrhs=9),
+    "fourier2d_N16_q5_5rhs": lambda: W.fourier_grid(16, d=2, q=5, nrhs=5),
+    "genradon3_N8_q4_3rhs": lambda: W.genradon3(8, q=4, nrhs=3),
 }
 
 
@@ -79,7 +85,8 @@ def test_fp64_forward_parity(torch_dev, orc, name):
 
 
 @pytest.mark.parametrize("name", ["fourier1d_N64_q8", "C1_fourier2d_N64_q5", "hypradon2_N32_q5",
-                                  "hypradon2_N64_q3_3rhs", "genradon3_N8_q4", "separable2d_N16_q3"])
+                                  "hypradon2_N64_q3_3rhs", "genradon3_N8_q4", "separable2d_N16_q3",
+                                  "hypradon2_N32_q5_9rhs"])
 def test_fp64_adjoint_parity(torch_dev, orc, name):
     w = SMALL[name]()
     print(f"[case] fp64 adjoint {name}", flush=True)
@@ -92,7 +99,7 @@ def test_fp64_adjoint_parity(torch_dev, orc, name):
 
 
 @pytest.mark.parametrize("name", ["C1_fourier2d_N64_q5", "hypradon2_N128_q5", "genradon3_N16_q4_2rhs",
-                                  "fourier1d_N64_q8"])
+                                  "fourier1d_N64_q8", "hypradon2_N32_q5_9rhs", "fourier2d_N32_q6_9rhs"])
 def test_fp32_forward_parity(torch_dev, orc, name):
     w = SMALL[name]()
     print(f"[case] fp32 forward {name}", flush=True)
@@ -217,3 +224,31 @@ def test_C2_gap_to_direct_sum(torch_dev, orc, c2_oracle):
     e = rel(f[:, idx], fd)
     print(f"  gap gpu {e:.3e} oracle {eps_q:.3e}", flush=True)
     assert e <= eps_q + 1e-12
+
+
+@pytest.fixture(scope="module")
+def c3_oracle(orc):
+    w = W.C3()
+    print("[case] oracle C3 (full size)", flush=True)
+    return w, oracle_run(orc, w)
+
+
+def test_C3_full_parity(torch_dev, c3_oracle):
+    """3-D generalized-Radon workload at full size (N = 64, q = 4), both modes."""
+    w, ref = c3_oracle
+    for prec, tol in (("fp64", FP64_TOL), ("fp32", FP32_TOL)):
+        print(f"[case] {prec} forward C3 full", flush=True)
+        e = rel(gpu_run(torch_dev, w, prec), ref)
+        print(f"  rel err {e:.3e}", flush=True)
+        assert e < tol
+
+
+def test_C1_direct_sum_and_fft(torch_dev, orc):
+    """C1 (Fourier, uniform grids): the GPU butterfly against the exact DFT
+    (numpy FFT) within the oracle butterfly's own error."""
+    w = W.C1(nrhs=2)
+    f = gpu_run(torch_dev, w, "fp64")
+    fb = oracle_run(orc, w)
+    for s_ in range(2):
+        exact = w.N ** 2 * np.fft.ifftn(w.g[s_].reshape(w.N, w.N)).reshape(-1)
+        assert rel(f[s_], exact) <= rel(fb[s_], exact) + 1e-12

@@ -27,7 +27,7 @@ def rel(a, b):
 
 @pytest.mark.parametrize("q", [1, 2, 3, 5, 8, 13])
 def test_nodes_are_roots_of_chebyshev_T(orc, q):
-    """Chebyshev grid (Sec. 2, analytic interpolation): first-kind nodes are the
+    """Chebyshev grid (Sec. 1.4, analytic interpolation): first-kind nodes are the
     roots of T_q, as computed by numpy's Chebyshev module."""
     z = np.sort(orc.nodes(q))
     roots = np.sort(npcheb.Chebyshev.basis(q).roots().real)
@@ -35,7 +35,7 @@ def test_nodes_are_roots_of_chebyshev_T(orc, q):
 
 
 def test_phase_handworked_values(orc):
-    """Phase definitions (Sec. 4.1, Sec. 4.2, Fourier kernel of Sec. 4) at
+    """Phase definitions (Sec. 3.1, Sec. 3.2, Fourier kernel of Sec. 3) at
     points worked out by hand."""
     with open(os.path.join(GOLDEN, "phase_handworked.json")) as fh:
         cases = json.load(fh)["cases"]
@@ -143,7 +143,7 @@ def test_butterfly_operation_counts(orc):
     """Exact counts of the dense form: phase evaluations
     n_src + n_tgt + P (2r + L (2^d+1) r + r^2); real x complex MACs
     (n_src + n_tgt) r + P L 2^d r^2; switch complex MACs P r^2 (Sec. 1 and
-    Sec. 2: O(r N^d) ends, O(r^2 N^d) per stage, log2 N stages)."""
+    Sec. 1.1: O(r N^d) ends, O(r^2 N^d) per stage, log2 N stages)."""
     for w in (W.fourier_grid(16, d=1, q=4), W.hypradon2(8, q=3), W.genradon3(4, q=2),
               W.fourier_grid(1, d=2, q=3)):
         _, c = orc.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, w.y, w.g, w.x,
