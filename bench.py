@@ -34,37 +34,56 @@ TAU_FLOPS = {"fourier": lambda d: 2 * d - 1, "hypradon2": lambda d: 6, "genradon
 
 
 def phase_flops(phase: str, d: int) -> int:
-    """tau + reduction modulo 1 (2) + sine/cosine pair."""
+    """One phase factor: tau + reduction modulo 1 (2) + sine/cosine pair."""
     return TAU_FLOPS[phase](d) + 2 + SINCOS_FLOPS
 
 
+def tensor_macs(d: int, q: int) -> int:
+    """Real x complex multiply-adds per output vector of one merge-and-split
+    stage in tensor form: along each dimension a q x q transform onto both
+    halves, (2^(d+1) - 2) q^(d+1) in total (both halves of the algorithm)."""
+    return (2 ** (d + 1) - 2) * q ** (d + 1)
+
+
 def stage_flops(kind: str, phase: str, d: int, N: int, q: int, nrhs: int) -> float:
-    """Algorithmic flops of one merge-and-split stage over all N^d pairs.
-    Column space (first half): per output vector (2^d + 1) r phase factors
-    and (2^(d+1) - 2) q^(d+1) real x complex multiply-adds (tensor form);
-    row space (second half): the same phase count and 2^d d q^(d+1)."""
+    """Algorithmic flops of one merge-and-split stage over all N^d outputs.
+    Column space: (2^d + 1) r phase factors per output vector, each applied
+    to a value (complex multiply, 6 flops per right-hand side).  Row space,
+    on demodulated weights: 2^d r factors of a phase difference (one more
+    flop each) applied by complex multiply-add (8 flops), plus r evaluations
+    of tau alone (the parent-centre phase).  Both: the tensor-form
+    interpolation at 4 flops per real x complex multiply-add."""
     r, nc, P = q ** d, 2 ** d, N ** d
-    evals = P * (nc + 1) * r
-    macs = P * ((2 ** (d + 1) - 2) if kind == "first" else nc * d) * q ** (d + 1)
-    return evals * phase_flops(phase, d) + evals * nrhs * 6 + macs * nrhs * 4
+    macs = P * tensor_macs(d, q) * nrhs * 4
+    if kind == "first":
+        evals = P * (nc + 1) * r
+        return evals * phase_flops(phase, d) + evals * nrhs * 6 + macs
+    evals = P * nc * r
+    return evals * (phase_flops(phase, d) + 1) + P * r * TAU_FLOPS[phase](d) + evals * nrhs * 8 + macs
 
 
 def init_flops(phase, d, N, q, nrhs, n_src):
+    """Leaf initialisation: a phase factor per source point and per leaf node
+    (each applied by complex multiply) and r real x complex multiply-adds per
+    point (the Lagrange weights)."""
     r, P = q ** d, N ** d
     evals = n_src + P * r
     return evals * phase_flops(phase, d) + evals * nrhs * 6 + n_src * r * nrhs * 4
 
 
 def switch_flops(phase, d, N, q, nrhs):
+    """Middle switch: r^2 factors per pair (phase difference, one more flop)
+    applied by complex multiply-add, plus r evaluations of tau alone."""
     r, P = q ** d, N ** d
     evals = P * r * r
-    return evals * phase_flops(phase, d) + evals * nrhs * 8
+    return evals * (phase_flops(phase, d) + 1) + P * r * TAU_FLOPS[phase](d) + evals * nrhs * 8
 
 
 def final_flops(phase, d, N, q, nrhs, n_tgt):
-    r, P = q ** d, N ** d
-    evals = n_tgt + P * r
-    return evals * phase_flops(phase, d) + evals * nrhs * 6 + n_tgt * r * nrhs * 4
+    """Final evaluation on demodulated weights: one phase factor and r real x
+    complex multiply-adds per target, and the closing complex multiply."""
+    r = q ** d
+    return n_tgt * phase_flops(phase, d) + n_tgt * r * nrhs * 4 + n_tgt * nrhs * 6
 
 
 def kind_flops(kind: str, t: dict, w, n_src: int, n_tgt: int) -> float:

@@ -199,8 +199,11 @@ int bfly_plan(int d, int64_t N, const double* src_lo, const double* src_hi, cons
     p->tgt_lo[j] = tgt_lo[j];
     p->tgt_hi[j] = tgt_hi[j];
   }
-  // Chebyshev nodes of the first kind (the grid of Sec. 1.4)
+  // Chebyshev nodes of the first kind (the grid of Sec. 1.4), stored exactly
+  // antisymmetric, z[q-1-k] = -z[k] (the level kernels use the reflection)
   for (int k = 0; k < q; ++k) p->z[k] = std::cos((double)(2 * k + 1) * M_PI / (double)(2 * q));
+  for (int k = 0; k < q / 2; ++k) p->z[q - 1 - k] = -p->z[k];
+  if (q % 2) p->z[q / 2] = 0.0;
   *out = p;
   return ok();
 }

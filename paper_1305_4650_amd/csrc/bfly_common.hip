@@ -105,13 +105,14 @@ hipError_t bin_sources(const Geo& G, int64_t n_in, const double* pts_in, const W
   return hipGetLastError();
 }
 
-// Launch-shape overrides for tuning sweeps: BFLY_VB, BFLY_KFUSE, BFLY_LDS.
+// Launch-shape overrides for tuning sweeps: BFLY_UB (fusion units per
+// block), BFLY_KFUSE (stages per launch), BFLY_LDS (LDS budget in bytes).
 void tune_from_env(LevelArgs& la) {
-  static const int vb = [] { const char* v = getenv("BFLY_VB"); return v ? atoi(v) : 0; }();
+  static const int ub = [] { const char* v = getenv("BFLY_UB"); return v ? atoi(v) : 0; }();
   static const int kf = [] { const char* v = getenv("BFLY_KFUSE"); return v ? atoi(v) : 0; }();
-  if (kf >= 1 && kf <= 8) la.k_fuse = kf;
   static const int lds = [] { const char* v = getenv("BFLY_LDS"); return v ? atoi(v) : 0; }();
-  if (vb >= 1 && vb <= 64 && (vb & (vb - 1)) == 0) la.vb_target = vb;
+  if (ub >= 1 && ub <= 64) la.ub_force = ub;
+  if (kf >= 1 && kf <= 8) la.k_fuse = kf;
   if (lds >= 16384 && lds <= 163840) la.lds_budget = (size_t)lds;
 }
 

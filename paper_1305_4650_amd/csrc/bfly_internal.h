@@ -85,7 +85,7 @@ struct LevelArgs {
   double* vals_out = nullptr;
   int64_t ld_out = 0;
   hipStream_t stream = nullptr;
-  int vb_target = 16;            // weight vectors per workgroup block
+  int ub_force = 0;              // fusion units per workgroup block (0: chosen per launch)
   int k_fuse = 2;                // merge-and-split stages fused per launch (at most)
   size_t lds_budget = 81920;     // bytes of LDS per workgroup (two workgroups per CU)
 };
