@@ -142,6 +142,55 @@ int bfly_apply_adjoint(bfly_plan_t plan,
                        int64_t n_src, const double* y, void* g_out, int64_t ldg,
                        int nrhs, int prec, void* ws, size_t ws_bytes, void* stream);
 
+/* One instance of a batched apply (bfly_apply_batched): a forward apply
+ * (adjoint = 0: inputs g at the plan's sources, outputs f at its targets) or
+ * an adjoint apply (adjoint = 1: inputs f at the targets, outputs g at the
+ * sources), with the sizes, layouts and ownership of bfly_apply /
+ * bfly_apply_adjoint:
+ *  plan               any plan; instances may use different plans
+ *  nrhs               1 .. 4096
+ *  n_in, pts_in       input points, device double[n_in][d]
+ *  in, ld_in          device complex128 [nrhs][ld_in], ld_in >= n_in
+ *  n_out, pts_out     output points, device double[n_out][d]
+ *  out, ld_out        device complex128 [nrhs][ld_out], ld_out >= n_out,
+ *                     overwritten; must not alias any other buffer of the batch */
+typedef struct {
+  bfly_plan_t plan;
+  int adjoint;
+  int nrhs;
+  int64_t n_in;
+  const double* pts_in;
+  const void* in;
+  int64_t ld_in;
+  int64_t n_out;
+  const double* pts_out;
+  void* out;
+  int64_t ld_out;
+} bfly_batch_item;
+
+/* Device workspace, in bytes, for bfly_apply_batched on these n_items
+ * (host array) in precision prec.  Returns BFLY_OK, BFLY_EINVAL or
+ * BFLY_EDEVICE. */
+int bfly_batch_workspace_size(int n_items, const bfly_batch_item* items, int prec, size_t* bytes);
+
+/* Many applies at once, batched across instances: every instance gives the
+ * result bfly_apply or
+ * bfly_apply_adjoint would give it, bit for bit, but the instances are
+ * binned in one sort and their level stages run level-synchronously, one
+ * launch per step for all instances that share d, q, phase and direction,
+ * so small instances share the GPU.  The call enqueues kernels only (no
+ * allocation, no synchronisation, no host-to-device copy, no memset), so it
+ * may be captured in a HIP graph; a captured call reads its descriptors of
+ * pointers and sizes as they were at capture time.
+ *  n_items    1 .. 4096 instances (host array `items`)
+ *  prec       BFLY_FP64 or BFLY_FP32 for all of them
+ *  ws         ws_bytes >= bfly_batch_workspace_size(n_items, items, prec),
+ *             256-byte aligned
+ * Limits: total input points below 2^31, total leaves (sum of N^d) at most
+ * 2^31.  Returns BFLY_OK, BFLY_EINVAL, BFLY_EWORKSPACE or BFLY_EDEVICE. */
+int bfly_apply_batched(int n_items, const bfly_batch_item* items, int prec, void* ws, size_t ws_bytes,
+                       void* stream);
+
 /* Per-step timing, for profiling.  While enabled, every apply records a HIP
  * event pair around each kernel launch on its stream (a few microseconds of
  * overhead per launch).  bfly_timing_read waits for the recorded events and

@@ -7,6 +7,8 @@ the C ABI of include/bfly.h.  This package is the Python binding
 (``bfly.py``), the build script (``build.py``) and the seeded synthetic
 workloads (``workloads.py``).
 """
-from .bfly import (BFLY_FP32, BFLY_FP64, BflyError, Plan, bfly_apply, bfly_apply_adjoint,  # noqa: F401
-                   bfly_apply_autograd, bfly_last_error, bfly_plan, bfly_plan_destroy, bfly_plan_info,
-                   bfly_status_string, bfly_timing_enable, bfly_timing_read, bfly_workspace_size, lib)
+from .bfly import (BFLY_FP32, BFLY_FP64, Batch, BatchItem, BflyError, Plan, apply_batched,  # noqa: F401
+                   bfly_apply, bfly_apply_adjoint, bfly_apply_autograd, bfly_apply_batched,
+                   bfly_apply_batched_autograd, bfly_batch_workspace_size, bfly_last_error, bfly_plan,
+                   bfly_plan_destroy, bfly_plan_info, bfly_status_string, bfly_timing_enable, bfly_timing_read,
+                   bfly_workspace_size, lib)

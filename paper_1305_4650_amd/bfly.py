@@ -24,8 +24,8 @@ PHASES = {"fourier": 0, "hypradon2": 1, "genradon3": 2, "separable": 3}
 PRECISIONS = {"fp64": BFLY_FP64, "fp32": BFLY_FP32}
 
 EXPORTS = ("bfly_plan", "bfly_plan_destroy", "bfly_plan_info", "bfly_workspace_size", "bfly_apply",
-           "bfly_apply_adjoint", "bfly_timing_enable", "bfly_timing_read", "bfly_status_string",
-           "bfly_last_error")
+           "bfly_apply_adjoint", "bfly_batch_workspace_size", "bfly_apply_batched", "bfly_timing_enable",
+           "bfly_timing_read", "bfly_status_string", "bfly_last_error")
 STEP_NAMES = ("binning", "first", "second", "final")
 
 
@@ -36,6 +36,14 @@ class BflyError(RuntimeError):
 
 
 _lib = None
+
+
+class BatchItem(ctypes.Structure):
+    """bfly_batch_item of include/bfly.h."""
+    _fields_ = [("plan", ctypes.c_void_p), ("adjoint", ctypes.c_int), ("nrhs", ctypes.c_int),
+                ("n_in", ctypes.c_int64), ("pts_in", ctypes.c_void_p), ("in_", ctypes.c_void_p),
+                ("ld_in", ctypes.c_int64), ("n_out", ctypes.c_int64), ("pts_out", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("ld_out", ctypes.c_int64)]
 
 
 def lib() -> ctypes.CDLL:
@@ -61,6 +69,12 @@ def lib() -> ctypes.CDLL:
                              ctypes.c_size_t, vp]
     L.bfly_apply_adjoint.restype = ctypes.c_int
     L.bfly_apply_adjoint.argtypes = L.bfly_apply.argtypes
+    L.bfly_batch_workspace_size.restype = ctypes.c_int
+    L.bfly_batch_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(BatchItem), ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_size_t)]
+    L.bfly_apply_batched.restype = ctypes.c_int
+    L.bfly_apply_batched.argtypes = [ctypes.c_int, ctypes.POINTER(BatchItem), ctypes.c_int, vp, ctypes.c_size_t,
+                                     vp]
     L.bfly_timing_enable.restype = ctypes.c_int
     L.bfly_timing_enable.argtypes = [ctypes.c_int]
     L.bfly_timing_read.restype = ctypes.c_int
@@ -119,6 +133,17 @@ def bfly_apply_adjoint(plan, n_tgt, x, f_in, ldf, n_src, y, g_out, ldg, nrhs, pr
                        stream) -> None:
     _check(lib().bfly_apply_adjoint(plan, n_tgt, x, f_in, ldf, n_src, y, g_out, ldg, nrhs, prec, ws,
                                     ws_bytes, stream), "bfly_apply_adjoint")
+
+
+def bfly_batch_workspace_size(items, prec: int) -> int:
+    """items: a ctypes array of BatchItem."""
+    out = ctypes.c_size_t()
+    _check(lib().bfly_batch_workspace_size(len(items), items, prec, ctypes.byref(out)), "bfly_batch_workspace_size")
+    return out.value
+
+
+def bfly_apply_batched(items, prec: int, ws, ws_bytes, stream) -> None:
+    _check(lib().bfly_apply_batched(len(items), items, prec, ws, ws_bytes, stream), "bfly_apply_batched")
 
 
 def bfly_timing_enable(on: bool) -> None:
@@ -238,6 +263,49 @@ class Plan:
         return self._run(True, x, f, y, prec, out, workspace, stream)
 
 
+class Batch:
+    """Several applies run together by bfly_apply_batched.
+
+    items: sequence of (plan, adjoint, pts_in, vals_in, pts_out), with vals_in
+    (nrhs, n_in) complex128 and points as for Plan.apply / apply_adjoint.  The
+    outputs (nrhs, n_out) and the workspace are allocated here; run() writes
+    the outputs.  Pointers and sizes are fixed at construction, so a run() can
+    be captured in a HIP graph and replayed after the inputs are refilled."""
+
+    def __init__(self, items, prec="fp64", device=None):
+        torch = _torch()
+        self.prec = _prec_id(prec)
+        self.items = []
+        self.outs = []
+        arr = (BatchItem * len(items))()
+        for k, (plan, adjoint, pin, vin, pout) in enumerate(items):
+            pin = _points(pin, plan.d, f"item {k} input points")
+            pout = _points(pout, plan.d, f"item {k} output points")
+            vin, ldin = _values(vin, pin.shape[0], f"item {k} input values")
+            out = torch.empty((vin.shape[0], pout.shape[0]), dtype=torch.complex128, device=pin.device)
+            _, ldout = _values(out, pout.shape[0], f"item {k} output values")
+            arr[k] = BatchItem(plan.handle, int(bool(adjoint)), vin.shape[0], pin.shape[0], pin.data_ptr(),
+                               vin.data_ptr(), ldin, pout.shape[0], pout.data_ptr(), out.data_ptr(), ldout)
+            self.items.append((plan, pin, vin, pout))  # keep every buffer alive
+            self.outs.append(out)
+        self._arr = arr
+        nbytes = bfly_batch_workspace_size(arr, self.prec)
+        dev = device or (self.items[0][1].device if self.items else "cuda")
+        self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+
+    def run(self, stream=None):
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(self.workspace.device).cuda_stream
+        bfly_apply_batched(self._arr, self.prec, self.workspace.data_ptr(), self.workspace.numel(), stream)
+        return self.outs
+
+
+def apply_batched(items, prec="fp64"):
+    """Outputs of Batch(items, prec).run() (one call, fresh buffers)."""
+    return Batch(items, prec).run()
+
+
 def _make_autograd():
     torch = _torch()
 
@@ -264,6 +332,28 @@ def _make_autograd():
 
 
 _BflyApply = None
+_BflyBatchApply = None
+
+
+def _make_batch_autograd():
+    torch = _torch()
+
+    class BflyBatchApply(torch.autograd.Function):
+        """f_k = B_k g_k for every instance k in one batched apply; the
+        backward is one batched adjoint apply, grad_g_k = B'_k grad_f_k."""
+
+        @staticmethod
+        def forward(ctx, spec, prec, *gs):
+            ctx.spec, ctx.prec = spec, prec
+            items = [(plan, False, y, g.contiguous(), x) for (plan, y, x), g in zip(spec, gs)]
+            return tuple(Batch(items, prec).run())
+
+        @staticmethod
+        def backward(ctx, *grads):
+            items = [(plan, True, x, gf.contiguous(), y) for (plan, y, x), gf in zip(ctx.spec, grads)]
+            return (None, None, *Batch(items, ctx.prec).run())
+
+    return BflyBatchApply
 
 
 def bfly_apply_autograd(g, plan: Plan, y, x, prec="fp64"):
@@ -272,3 +362,12 @@ def bfly_apply_autograd(g, plan: Plan, y, x, prec="fp64"):
     if _BflyApply is None:
         _BflyApply = _make_autograd()
     return _BflyApply.apply(g, plan, y, x, prec)
+
+
+def bfly_apply_batched_autograd(gs, spec, prec="fp64"):
+    """Differentiable batched forward apply: spec = [(plan, y, x), ...], one g per
+    instance; returns the tuple of outputs (see BflyBatchApply)."""
+    global _BflyBatchApply
+    if _BflyBatchApply is None:
+        _BflyBatchApply = _make_batch_autograd()
+    return _BflyBatchApply.apply(spec, prec, *gs)

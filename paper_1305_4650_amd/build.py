@@ -30,7 +30,8 @@ COMMON = [
     "-I", os.path.join(ROOT, "include"),
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
-SOURCES = ["bfly_d2.hip", "bfly_d3.hip", "bfly_d1.hip", "bfly_common.hip", "bfly_api.cpp", "bfly_timing.cpp"]
+SOURCES = ["bfly_d2.hip", "bfly_d2_batch.hip", "bfly_d3.hip", "bfly_d3_batch.hip", "bfly_d1.hip",
+           "bfly_d1_batch.hip", "bfly_common.hip", "bfly_api.cpp", "bfly_timing.cpp"]
 
 
 def build(verbose: bool = True, jobs: int = 6, out: str = LIB, defines=(), build_dir: str = BUILD) -> str:

@@ -6,6 +6,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/bfly.h"
 #include "bfly_internal.h"
@@ -160,6 +162,143 @@ int apply_common(bfly_plan_t plan, bool adjoint, int64_t n_in, const double* pin
   return ok();
 }
 
+// ---- batched applies ----
+
+struct BLayout {
+  std::vector<size_t> w;     // weights of each instance
+  std::vector<uint32_t> leafbase;
+  size_t keys = 0, keys_sorted = 0, idx = 0, perm = 0, offs = 0, desc = 0, tmp = 0, total = 0, tmp_bytes = 0;
+  int64_t n_total = 0;
+  uint64_t leaves = 0;
+};
+
+int check_item(const bfly_batch_item& it, int k) {
+  if (int rc = check_plan(it.plan)) return fail(rc, "item %d: plan is NULL", k);
+  if (it.adjoint != 0 && it.adjoint != 1) return fail(BFLY_EINVAL, "item %d: adjoint must be 0 or 1", k);
+  if (it.nrhs < 1 || it.nrhs > 4096) return fail(BFLY_EINVAL, "item %d: nrhs must be in [1, 4096]", k);
+  if (it.n_in < 0 || it.n_in >= ((int64_t)1 << 31)) return fail(BFLY_EINVAL, "item %d: n_in out of range", k);
+  if (it.n_out < 0 || it.n_out >= ((int64_t)1 << 31)) return fail(BFLY_EINVAL, "item %d: n_out out of range", k);
+  if (it.ld_in < it.n_in || it.ld_in < 1) return fail(BFLY_EINVAL, "item %d: ld_in < n_in", k);
+  if (it.ld_out < it.n_out || it.ld_out < 1) return fail(BFLY_EINVAL, "item %d: ld_out < n_out", k);
+  if (it.n_in > 0 && (!it.pts_in || !it.in)) return fail(BFLY_EINVAL, "item %d: input points or values are NULL", k);
+  if (it.n_out > 0 && (!it.pts_out || !it.out))
+    return fail(BFLY_EINVAL, "item %d: output points or values are NULL", k);
+  return BFLY_OK;
+}
+
+int batch_layout(int n, const bfly_batch_item* items, int prec, BLayout* out) {
+  if (n < 1 || n > 4096) return fail(BFLY_EINVAL, "n_items must be in [1, 4096]");
+  if (!items) return fail(BFLY_EINVAL, "items is NULL");
+  if (prec != BFLY_FP64 && prec != BFLY_FP32) return fail(BFLY_EINVAL, "unknown precision mode %d", prec);
+  BLayout L;
+  size_t off = 0;
+  for (int k = 0; k < n; ++k) {
+    if (int rc = check_item(items[k], k)) return rc;
+    const bfly_plan_s& p = *items[k].plan;
+    L.w.push_back(off);
+    off += up(bfly::weight_bytes(make_geo(p, items[k].adjoint != 0), items[k].nrhs, prec));
+    L.leafbase.push_back((uint32_t)L.leaves);
+    L.leaves += (uint64_t)1 << (p.d * p.L);
+    L.n_total += items[k].n_in;
+    if (L.leaves > ((uint64_t)1 << 31)) return fail(BFLY_EINVAL, "total leaves of the batch exceed 2^31");
+    if (L.n_total >= ((int64_t)1 << 31)) return fail(BFLY_EINVAL, "total input points of the batch reach 2^31");
+  }
+  int bits = 0;
+  while (bits < 32 && ((uint64_t)1 << bits) < L.leaves) ++bits;
+  hipError_t e = bfly::sort_storage_bytes(L.n_total, bits, &L.tmp_bytes);
+  if (e != hipSuccess) return fail(BFLY_EDEVICE, "sort storage query failed: %s", hipGetErrorString(e));
+  const size_t nt = (size_t)L.n_total;
+  L.keys = off;
+  off += up(4 * nt);
+  L.keys_sorted = off;
+  off += up(4 * nt);
+  L.idx = off;
+  off += up(4 * nt);
+  L.perm = off;
+  off += up(4 * nt);
+  L.offs = off;
+  off += up(4 * (L.leaves + 1));
+  L.desc = off;
+  off += up(2 * (size_t)n * sizeof(bfly::ItemDesc));
+  L.tmp = off;
+  off += up(L.tmp_bytes);
+  L.total = off;
+  *out = std::move(L);
+  return BFLY_OK;
+}
+
+int apply_batched(int n, const bfly_batch_item* items, int prec, void* ws, size_t ws_bytes, void* stream) {
+  BLayout L;
+  if (int rc = batch_layout(n, items, prec, &L)) return rc;
+  if (!ws || ws_bytes < L.total)
+    return fail(BFLY_EWORKSPACE, "workspace of %zu bytes given, %zu required", ws ? ws_bytes : (size_t)0,
+                L.total);
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(BFLY_EINVAL, "workspace must be 256-byte aligned");
+  if (int rc = check_sticky()) return rc;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  bfly::Work w;
+  w.keys = reinterpret_cast<uint32_t*>(base + L.keys);
+  w.keys_sorted = reinterpret_cast<uint32_t*>(base + L.keys_sorted);
+  w.idx = reinterpret_cast<int32_t*>(base + L.idx);
+  w.perm = reinterpret_cast<int32_t*>(base + L.perm);
+  w.offs = reinterpret_cast<int32_t*>(base + L.offs);
+  w.sort_tmp = base + L.tmp;
+  w.sort_tmp_bytes = L.tmp_bytes;
+  std::vector<bfly::Geo> geo(n);
+  std::vector<bfly::BinInst> bins(n);
+  std::vector<bfly::BatchInst> inst(n);
+  for (int k = 0; k < n; ++k) {
+    const bfly_batch_item& it = items[k];
+    geo[k] = make_geo(*it.plan, it.adjoint != 0);
+    bins[k].pts = it.pts_in;
+    bins[k].n = it.n_in;
+    bins[k].G = &geo[k];
+    bins[k].leafbase = L.leafbase[k];
+    bfly::BatchInst& b = inst[k];
+    b.G = geo[k];
+    b.W = base + L.w[k];
+    b.nrhs = it.nrhs;
+    b.pts_in = it.pts_in;
+    b.vals_in = static_cast<const double*>(it.in);
+    b.ld_in = it.ld_in;
+    b.offs = w.offs + L.leafbase[k];
+    b.n_out = it.n_out;
+    b.pts_out = it.pts_out;
+    b.vals_out = static_cast<double*>(it.out);
+    b.ld_out = it.ld_out;
+  }
+  hipError_t e = bfly::bin_batch(bins.data(), n, L.n_total, L.leaves, w, st);
+  if (e != hipSuccess) return fail(BFLY_EDEVICE, "binning launch failed: %s", hipGetErrorString(e));
+  // groups of instances sharing d, q, phase and direction, in order of first appearance
+  std::vector<int> done(n, 0);
+  int desc_next = 0;
+  for (int k = 0; k < n && e == hipSuccess; ++k) {
+    if (done[k]) continue;
+    std::vector<bfly::BatchInst> grp;
+    for (int j = k; j < n; ++j) {
+      const bfly::Geo& a = inst[k].G;
+      const bfly::Geo& b = inst[j].G;
+      if (!done[j] && a.d == b.d && a.q == b.q && a.phase == b.phase && a.adj == b.adj) {
+        grp.push_back(inst[j]);
+        done[j] = 1;
+      }
+    }
+    bfly::BatchGroup bg;
+    bg.inst = grp.data();
+    bg.n = (int)grp.size();
+    bg.perm = w.perm;
+    bg.desc = reinterpret_cast<bfly::ItemDesc*>(base + L.desc) + desc_next;
+    bg.stream = st;
+    bfly::tune_batch_from_env(bg);
+    desc_next += 2 * bg.n;
+    const int d = grp[0].G.d;
+    e = d == 1 ? bfly::run_batch_d1(bg, prec) : (d == 2 ? bfly::run_batch_d2(bg, prec) : bfly::run_batch_d3(bg, prec));
+  }
+  if (e != hipSuccess) return fail(BFLY_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
 }  // namespace
 
 extern "C" {
@@ -246,6 +385,19 @@ int bfly_apply_adjoint(bfly_plan_t plan, int64_t n_tgt, const double* x, const v
                        int64_t n_src, const double* y, void* g_out, int64_t ldg, int nrhs, int prec, void* ws,
                        size_t ws_bytes, void* stream) {
   return apply_common(plan, true, n_tgt, x, f_in, ldf, n_src, y, g_out, ldg, nrhs, prec, ws, ws_bytes, stream);
+}
+
+int bfly_batch_workspace_size(int n_items, const bfly_batch_item* items, int prec, size_t* bytes) {
+  if (!bytes) return fail(BFLY_EINVAL, "bytes is NULL");
+  BLayout L;
+  if (int rc = batch_layout(n_items, items, prec, &L)) return rc;
+  *bytes = L.total;
+  return ok();
+}
+
+int bfly_apply_batched(int n_items, const bfly_batch_item* items, int prec, void* ws, size_t ws_bytes,
+                       void* stream) {
+  return apply_batched(n_items, items, prec, ws, ws_bytes, stream);
 }
 
 int bfly_timing_enable(int on) {

@@ -23,13 +23,14 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Radix sort of the leaf keys: rocPRIM's onesweep algorithm above 64 Ki
-// points (its default switches from merge sort only above 1 Mi; on MI355X
-// the whole binning of 1 Mi points with 20-bit keys takes 0.13 ms this way,
-// 0.16 ms with the ~20 merge passes).  The same configuration sizes the
-// scratch in sort_storage_bytes.
+// Sort of the leaf keys: rocPRIM's radix_sort_pairs restricted to its merge
+// sort algorithm at every size.  Its onesweep algorithm (the default above
+// 1 Mi keys) clears scratch with hipMemsetAsync, and memset nodes in a
+// captured graph are avoided here; the merge sort launches kernels only.
+// (MI355X, 1 Mi 20-bit keys: 0.16 ms for the whole binning; onesweep 0.13.)
+// The same configuration sizes the scratch in sort_storage_bytes.
 using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
-                                              rocprim::default_config, 65536>;
+                                              rocprim::default_config, ~size_t(0)>;
 
 // leaf index along one dimension: floor((v - lo) / extent * n), clamped to
 // [0, n-1]; NaN goes to 0
@@ -113,6 +114,54 @@ hipError_t bin_sources(const Geo& G, int64_t n_in, const double* pts_in, const W
   return hipGetLastError();
 }
 
+// ---- batched binning: all instances' points in one sort ----
+struct BinItem {
+  const double* pts;
+  int64_t n, pbase;   // points, and the first global index of this instance
+  uint32_t leafbase;
+  int d, L;
+  double slo[3], sD[3];
+};
+constexpr int kBinItems = 16;
+struct BinArgs {
+  int n;
+  BinItem it[kBinItems];
+};
+
+__global__ __launch_bounds__(kBlock) void k_bin_batch(const BinArgs a, int64_t g0, int64_t g1,
+                                                      uint32_t* __restrict__ keys, int32_t* __restrict__ idx) {
+  const int64_t g = g0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= g1) return;
+  int k = 0;
+  while (k + 1 < a.n && a.it[k + 1].pbase <= g) ++k;
+  const BinItem& it = a.it[k];
+  const int64_t j = g - it.pbase;
+  const int64_t N = (int64_t)1 << it.L;
+  int64_t b[3] = {0, 0, 0};
+  for (int i = 0; i < it.d; ++i) b[i] = bin1(it.pts[j * it.d + i], it.slo[i], it.sD[i], N);
+  uint32_t m = 0;
+  for (int l = 0; l < it.L; ++l)
+    for (int i = 0; i < it.d; ++i) m |= (uint32_t)((b[i] >> l) & 1) << (it.d * l + i);
+  keys[g] = it.leafbase + m;
+  idx[g] = (int32_t)j;
+}
+
+// descriptors travel in kernel arguments, kPutItems at a time
+constexpr int kPutItems = 8;
+struct PutArgs {
+  int n;
+  ItemDesc d[kPutItems];
+};
+__global__ void k_put_items(const PutArgs a, ItemDesc* __restrict__ dst) {
+  constexpr int words = (int)(sizeof(ItemDesc) / sizeof(uint32_t));
+  static_assert(sizeof(ItemDesc) % sizeof(uint32_t) == 0, "descriptor size");
+  for (int k = 0; k < a.n; ++k) {
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(&a.d[k]);
+    uint32_t* o = reinterpret_cast<uint32_t*>(dst + k);
+    for (int w = threadIdx.x; w < words; w += blockDim.x) o[w] = s[w];
+  }
+}
+
 // Launch-shape overrides for tuning sweeps: BFLY_UB (fusion units per
 // block), BFLY_KFUSE (stages per launch), BFLY_LDS (LDS budget in bytes).
 void tune_from_env(LevelArgs& la) {
@@ -125,6 +174,67 @@ void tune_from_env(LevelArgs& la) {
 }
 
 }  // namespace
+
+hipError_t put_items(ItemDesc* dst, const ItemDesc* src, int n, hipStream_t st) {
+  for (int k0 = 0; k0 < n; k0 += kPutItems) {
+    PutArgs a;
+    a.n = std::min(kPutItems, n - k0);
+    for (int k = 0; k < a.n; ++k) a.d[k] = src[k0 + k];
+    k_put_items<<<1, 128, 0, st>>>(a, dst + k0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t bin_batch(const BinInst* bi, int n, int64_t n_total, uint64_t leaves_total, const Work& w,
+                     hipStream_t st) {
+  StepTimer tb(kStepBin, st);
+  int64_t pbase = 0;
+  for (int k0 = 0; k0 < n; k0 += kBinItems) {
+    BinArgs a;
+    a.n = std::min(kBinItems, n - k0);
+    const int64_t g0 = pbase;
+    for (int k = 0; k < a.n; ++k) {
+      const BinInst& b = bi[k0 + k];
+      BinItem& it = a.it[k];
+      it.pts = b.pts;
+      it.n = b.n;
+      it.pbase = pbase;
+      it.leafbase = b.leafbase;
+      it.d = b.G->d;
+      it.L = b.G->L;
+      for (int i = 0; i < 3; ++i) {
+        it.slo[i] = b.G->slo[i];
+        it.sD[i] = b.G->sD[i];
+      }
+      pbase += b.n;
+    }
+    if (pbase > g0) k_bin_batch<<<blocks_for(pbase - g0), kBlock, 0, st>>>(a, g0, pbase, w.keys, w.idx);
+  }
+  if (n_total > 0) {
+    int bits = 0;
+    while (bits < 32 && ((uint64_t)1 << bits) < leaves_total) ++bits;
+    if (bits > 0) {
+      size_t tmp = w.sort_tmp_bytes;
+      const hipError_t e = rocprim::radix_sort_pairs<SortConfig>(w.sort_tmp, tmp, w.keys, w.keys_sorted, w.idx,
+                                                                 w.perm, (unsigned)n_total, 0, bits, st);
+      if (e != hipSuccess) return e;
+    } else {
+      k_iota<<<blocks_for(n_total), kBlock, 0, st>>>(n_total, w.perm, w.keys_sorted);
+    }
+    k_offsets<<<blocks_for(n_total), kBlock, 0, st>>>(n_total, (int64_t)leaves_total, w.keys_sorted, w.offs);
+  } else {
+    k_offsets<<<blocks_for((int64_t)leaves_total + 1), kBlock, 0, st>>>(0, (int64_t)leaves_total, nullptr, w.offs);
+  }
+  return hipGetLastError();
+}
+
+void tune_batch_from_env(BatchGroup& bg) {
+  LevelArgs la;
+  tune_from_env(la);
+  bg.k_fuse = la.k_fuse;
+  bg.lds_budget = la.lds_budget;
+  bg.ub_force = la.ub_force;
+}
 
 size_t weight_bytes(const Geo& g, int nrhs, int prec) {
   const size_t P = (size_t)1 << (g.d * g.L);

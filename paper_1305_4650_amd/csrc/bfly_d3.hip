@@ -1,39 +1,10 @@
-// Fused level kernels for d = 3: one instantiation per supported q and
-// precision, plus phase-specialised ones for the benchmark workloads.  The
-// expensive phases (hyperbolic and generalized Radon) process right-hand
-// sides in chunks that share their phase factors; the Fourier phase costs a
-// few flops, so chunking it only adds register pressure (measured slower).
-#include "bfly_fused.inc"
+// Level kernels for single applies, d = 3.
+#include "bfly_d3.inc"
 
 namespace bfly {
-namespace {
-
-template <int Q>
-hipError_t run_q(const LevelArgs& la, int prec) {
-  const int ph = la.G->phase;
-  (void)ph;
-  if constexpr (Q == 4) {
-    if (ph == 2)
-      return prec == 0 ? fz::run_levels_t<3, Q, double, 2, BFLY_RHS_CHUNK_FP64>(la) : fz::run_levels_t<3, Q, float, 2, BFLY_RHS_CHUNK_FP32>(la);
-  }
-  return prec == 0 ? fz::run_levels_t<3, Q, double, -1, 1>(la) : fz::run_levels_t<3, Q, float, -1, 1>(la);
-}
-
-}  // namespace
 
 hipError_t run_levels_d3(const LevelArgs& la, int prec) {
-  switch (la.G->q) {
-    case 2:
-      return run_q<2>(la, prec);
-    case 3:
-      return run_q<3>(la, prec);
-    case 4:
-      return run_q<4>(la, prec);
-    case 5:
-      return run_q<5>(la, prec);
-    default:
-      return hipErrorInvalidValue;
-  }
+  return on_d3(fz::SingleOp{la}, la.G->q, la.G->phase, prec);
 }
 
 }  // namespace bfly

@@ -93,6 +93,72 @@ hipError_t run_levels_d1(const LevelArgs& la, int prec);
 hipError_t run_levels_d2(const LevelArgs& la, int prec);
 hipError_t run_levels_d3(const LevelArgs& la, int prec);
 
+// ---- batched applies: many instances, level-synchronous launches ----
+
+// One instance of a batched apply after binning (host side).
+struct BatchInst {
+  Geo G;
+  void* W = nullptr;                 // this instance's weights
+  int nrhs = 1;
+  const double* pts_in = nullptr;
+  const double* vals_in = nullptr;   // complex128 [nrhs][ld_in]
+  int64_t ld_in = 0;
+  const int32_t* offs = nullptr;     // CSR offsets of this instance's source leaves
+  int64_t n_out = 0;
+  const double* pts_out = nullptr;
+  double* vals_out = nullptr;        // complex128 [nrhs][ld_out]
+  int64_t ld_out = 0;
+};
+
+// Device descriptor of one (instance, range of right-hand sides) of a
+// batched apply; the batched level kernels read it with scalar loads.
+struct ItemDesc {
+  Geo G;
+  void* W;                 // weights, shifted to the first right-hand side of the range
+  const double2* vals_in;  // input values, shifted likewise
+  double2* vals_out;       // output values, shifted likewise
+  const double* pts_in;
+  const double* pts_out;
+  const int32_t* offs;
+  int64_t ld_in, ld_out, n_out;
+  int nrhs;                // right-hand-side stride of W
+  int chunks;              // chunks of RC right-hand sides in the range
+};
+
+// Instances that share d, q, phase and role (forward or adjoint).
+struct BatchGroup {
+  const BatchInst* inst = nullptr;
+  int n = 0;
+  const int32_t* perm = nullptr;  // all instances' input points sorted by (instance, leaf)
+  ItemDesc* desc = nullptr;       // device room for 2 n descriptors
+  hipStream_t stream = nullptr;
+  int k_fuse = 2;
+  size_t lds_budget = 81920;
+  int ub_force = 0;
+};
+hipError_t run_batch_d1(const BatchGroup& bg, int prec);
+hipError_t run_batch_d2(const BatchGroup& bg, int prec);
+hipError_t run_batch_d3(const BatchGroup& bg, int prec);
+
+// Copy n descriptors from host memory to device memory through kernel
+// arguments (no host-to-device copy, so the call can be captured).
+hipError_t put_items(ItemDesc* dst, const ItemDesc* src, int n, hipStream_t st);
+
+// Input points of one instance for the batched binning.
+struct BinInst {
+  const double* pts = nullptr;
+  int64_t n = 0;
+  const Geo* G = nullptr;
+  uint32_t leafbase = 0;  // sum of the leaf counts of the instances before it
+};
+// Bin all instances' input points in one sort: key = leaf base + leaf
+// Morton index, value = the point's index within its instance; w.offs gets
+// leaves_total + 1 CSR offsets.
+hipError_t bin_batch(const BinInst* bi, int n, int64_t n_total, uint64_t leaves_total, const Work& w,
+                     hipStream_t st);
+// Launch-shape overrides (BFLY_UB, BFLY_KFUSE, BFLY_LDS) for batched applies.
+void tune_batch_from_env(BatchGroup& bg);
+
 // Enqueue one apply (binning, initialisation, stages, switch, final
 // evaluation) on `stream`.  Inputs were validated by the caller.
 hipError_t run_apply(const Geo& g, int prec, int64_t n_in, const double* pts_in,

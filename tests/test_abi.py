@@ -114,3 +114,46 @@ def test_binding_has_no_cpu_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         P.Plan(2, 16, BOX2, TBOX2, "hypradon2", 4)
+
+
+def test_batched_rejects_invalid_arguments_on_host():
+    """bfly_apply_batched / bfly_batch_workspace_size validate every item on
+    the host before any HIP call; the pointers are never dereferenced."""
+    p = P.Plan(2, 16, BOX2, TBOX2, "hypradon2", 4)
+    L = B.lib()
+    fake = 0x1000
+
+    def item(**kw):
+        a = dict(plan=p.handle, adjoint=0, nrhs=1, n_in=256, pts_in=fake, in_=fake, ld_in=256, n_out=256,
+                 pts_out=fake, out=fake, ld_out=256)
+        a.update(kw)
+        return B.BatchItem(**a)
+
+    def call(*its, prec=0, n=None):
+        arr = (B.BatchItem * len(its))(*its)
+        return L.bfly_apply_batched(len(its) if n is None else n, arr, prec, ctypes.c_void_p(fake), 1 << 40, None)
+
+    assert call(item(nrhs=0)) == B.BFLY_EINVAL
+    assert call(item(nrhs=5000)) == B.BFLY_EINVAL
+    assert call(item(adjoint=2)) == B.BFLY_EINVAL
+    assert call(item(ld_in=10)) == B.BFLY_EINVAL
+    assert call(item(ld_out=10)) == B.BFLY_EINVAL
+    assert call(item(n_out=-1)) == B.BFLY_EINVAL
+    assert call(item(n_in=1 << 31)) == B.BFLY_EINVAL
+    assert call(item(pts_in=None)) == B.BFLY_EINVAL
+    assert call(item(out=None)) == B.BFLY_EINVAL
+    assert call(item(plan=None)) == B.BFLY_EINVAL
+    assert call(item(), prec=9) == B.BFLY_EINVAL
+    assert call(item(), n=0) == B.BFLY_EINVAL
+    assert call(item(), item(nrhs=0)) == B.BFLY_EINVAL
+    assert "item 1" in P.bfly_last_error()
+    assert L.bfly_apply_batched(1, None, 0, ctypes.c_void_p(fake), 1 << 40, None) == B.BFLY_EINVAL
+    arr = (B.BatchItem * 1)(item(nrhs=0))
+    out = ctypes.c_size_t()
+    assert L.bfly_batch_workspace_size(1, arr, 0, ctypes.byref(out)) == B.BFLY_EINVAL
+
+
+def test_batch_item_layout_matches_header():
+    """The ctypes mirror of bfly_batch_item has the C layout (LP64)."""
+    assert ctypes.sizeof(B.BatchItem) == 80
+    assert B.BatchItem.n_in.offset == 16 and B.BatchItem.ld_out.offset == 72

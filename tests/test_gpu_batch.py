@@ -1,0 +1,145 @@
+"""Batched applies (bfly_apply_batched): many instances of uneven size, in
+both directions, binned in one sort and run level-synchronously.  Every
+instance must give exactly what its own bfly_apply / bfly_apply_adjoint gives
+(the arithmetic per weight vector is the same), the oracle agrees to the
+usual tolerance, a captured HIP graph replays correctly, and the batched
+autograd function equals the per-instance one."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1305_4650_amd as P
+from paper_1305_4650_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _instances():
+    """Uneven mix: hyperbolic Radon at N = 8..64 (nrhs 1, 3, 5: chunked and
+    remainder right-hand sides), one adjoint, one Fourier instance (another
+    group), one N = 1 instance (no stages)."""
+    out = []
+    for i, (N, nrhs) in enumerate([(8, 1), (32, 3), (16, 5), (64, 2), (32, 1)]):
+        w = W.hypradon2(N, q=5, nrhs=nrhs, config_id=900 + i)
+        out.append((w, False))
+    out.append((W.hypradon2(16, q=5, nrhs=2, config_id=910), True))
+    out.append((W.fourier_grid(32, d=2, q=5, nrhs=2, config_id=911), False))
+    out.append((W.hypradon2(1, q=3, nrhs=1, config_id=912), False))
+    return out
+
+
+def _plan(w):
+    return P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+
+
+def _items(insts, gen):
+    items, ref = [], []
+    for w, adj in insts:
+        plan = _plan(w)
+        y, x = _dev(w.y), _dev(w.x)
+        if adj:
+            f = W.random_rhs(gen, w.nrhs, x.shape[0])
+            items.append((plan, True, x, _dev(f), y))
+        else:
+            items.append((plan, False, y, _dev(w.g), x))
+        ref.append(plan)
+    return items
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_equals_single_applies_bitwise(prec):
+    insts = _instances()
+    items = _items(insts, np.random.default_rng(7))
+    outs = P.apply_batched(items, prec)
+    torch.cuda.synchronize()
+    for k, (plan, adj, pin, vin, pout) in enumerate(items):
+        single = (plan.apply_adjoint(pin, vin, pout, prec) if adj else plan.apply(pin, vin, pout, prec))
+        torch.cuda.synchronize()
+        assert torch.equal(outs[k], single), f"instance {k} (N={plan.N}, adjoint={adj})"
+
+
+def test_batched_matches_oracle(orc):
+    insts = _instances()[:3]
+    items = _items(insts, np.random.default_rng(8))
+    outs = P.apply_batched(items, "fp64")
+    for k, ((w, adj), out) in enumerate(zip(insts, outs)):
+        ref = orc.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, w.y, w.g, w.x)
+        got = out.cpu().numpy()
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-12, k
+
+
+def test_batched_graph_replays(prec="fp32"):
+    """Capture one batched apply in a HIP graph; refill the inputs and replay
+    it several times, with eager work and synchronisations in between; every
+    replay equals an eager batched apply on the same inputs."""
+    insts = _instances()[:5]
+    gen = np.random.default_rng(9)
+    items = _items(insts, gen)
+    batch = P.Batch(items, prec)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch.run()  # warm-up (library attributes, kernels loaded)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.run()
+    eager = P.Batch(items, prec)  # same input tensors, its own outputs and workspace
+    for rep in range(3):
+        for (plan, adj, pin, vin, pout) in items:
+            vin.copy_(_dev(W.random_rhs(gen, vin.shape[0], vin.shape[1])))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        ref = eager.run()
+        torch.cuda.synchronize()
+        for k in range(len(items)):
+            assert torch.equal(batch.outs[k], ref[k]), f"replay {rep}, instance {k}"
+
+
+def test_batched_autograd_equals_per_instance():
+    """The least-squares gradient through the batched apply (backward = one
+    batched adjoint apply) equals the per-instance autograd gradients."""
+    insts = [(W.hypradon2(N, q=5, nrhs=2, config_id=920 + i), False) for i, N in enumerate([8, 16, 32])]
+    spec, gs, ds = [], [], []
+    gen = np.random.default_rng(10)
+    for w, _ in insts:
+        plan = _plan(w)
+        y, x = _dev(w.y), _dev(w.x)
+        spec.append((plan, y, x))
+        gs.append(_dev(w.g).requires_grad_(True))
+        ds.append(_dev(W.random_rhs(gen, w.nrhs, x.shape[0])))
+    fs = P.bfly_apply_batched_autograd(gs, spec, "fp64")
+    loss = sum(0.5 * (f - d).abs().pow(2).sum() for f, d in zip(fs, ds))
+    loss.backward()
+    for (plan, y, x), g, d in zip(spec, gs, ds):
+        g1 = g.detach().clone().requires_grad_(True)
+        f1 = P.bfly_apply_autograd(g1, plan, y, x, "fp64")
+        (0.5 * (f1 - d).abs().pow(2).sum()).backward()
+        assert torch.equal(g.grad, g1.grad)
+
+
+@pytest.mark.parametrize("prec", ["fp32"])
+def test_c5_batch_equals_single_applies(prec):
+    """The uneven batch at its real shape: 48 hyperbolic-Radon instances with
+    N drawn from {128, 256, 512, 1024}, q = 5, 8 right-hand sides, in one
+    batched apply; each instance equals its own apply bit for bit (checked on
+    every instance)."""
+    sizes = W.C5_sizes()
+    insts = [(W.C5_instance(i, int(N)), False) for i, N in enumerate(sizes)]
+    items = _items(insts, np.random.default_rng(11))
+    print(f"[c5] {len(items)} instances, {int(sum(int(N) ** 2 for N in sizes))} points x 8 rhs", flush=True)
+    outs = P.apply_batched(items, prec)
+    torch.cuda.synchronize()
+    for k, (plan, adj, pin, vin, pout) in enumerate(items):
+        single = plan.apply(pin, vin, pout, prec)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[k], single), f"instance {k} (N={plan.N})"
+    del outs
