@@ -138,6 +138,56 @@ def time_steps(fn, torch, steps: int, warmup: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
+def measure_c5(torch, P, W, dev, steps: int, warmup: int) -> dict:
+    """The uneven batch: 48 hyperbolic-Radon instances (N from {128, 256,
+    512, 1024}, q = 5, 8 right-hand sides) in one batched apply, eagerly and
+    as a replayed HIP graph, against the 48 applies issued one after another."""
+    t0 = time.time()
+    sizes = W.C5_sizes()
+    plans = {int(N): P.Plan(2, int(N), ([1.0, 0.0], [2.0, 1.0]), ([0.0, 0.0], [1.0, 1.0]), "hypradon2", 5)
+             for N in set(sizes.tolist())}
+    items = []
+    for i, N in enumerate(sizes):
+        w = W.C5_instance(i, int(N))
+        items.append((plans[int(N)], False, torch.from_numpy(w.y).to(dev), torch.from_numpy(w.g).to(dev),
+                      torch.from_numpy(w.x).to(dev)))
+    pts = int(sum(int(N) ** 2 for N in sizes)) * 8
+    print(f"[bench] C5: {len(items)} instances, {pts // 8} points x 8 rhs ({time.time() - t0:.1f}s to generate)",
+          file=sys.stderr, flush=True)
+    out = {"workload": "48 hyperbolic-Radon instances, N drawn from {128,256,512,1024}, q=5, 8 right-hand sides",
+           "instances": len(items), "points_x_rhs": pts, "unit": "Mpoints/s"}
+    for prec in ("fp32", "fp64"):
+        batch = P.Batch(items, prec)
+        ms_b = time_steps(batch.run, torch, steps, warmup)
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            batch.run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            batch.run()
+        ms_g = time_steps(graph.replay, torch, steps, warmup)
+        singles = []
+        for (plan, _, y, g, x) in items:
+            ws = plan.workspace(y.shape[0], g.shape[0], prec, device=dev)
+            singles.append((plan, y, g, x, torch.empty_like(g), ws))
+
+        def seq():
+            for plan, y, g, x, f, ws in singles:
+                plan.apply(y, g, x, prec, out=f, workspace=ws)
+
+        ms_s = time_steps(seq, torch, steps, warmup)
+        out[prec] = {"batched_ms": round(ms_b, 3), "graph_ms": round(ms_g, 3), "sequential_ms": round(ms_s, 3),
+                     "value": round(pts / ms_g / 1e3, 3)}
+        print(f"[bench] C5 {prec}: batched {ms_b:.2f} ms, graph {ms_g:.2f} ms, 48 single applies {ms_s:.2f} ms "
+              f"-> {pts / ms_g / 1e3:.1f} Mpoints/s", file=sys.stderr, flush=True)
+        del batch, graph, singles
+        torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +195,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (no rel err either)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (default: all in affinity)")
+    ap.add_argument("--no-c5", action="store_true", help="skip the batched 48-instance measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one plain device copy of 1 GiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -217,6 +268,8 @@ def main() -> int:
         print(f"[bench] oracle {t_cpu:.1f}s on {cores} threads; rel err fp64 "
               f"{res['fp64']['rel_err']:.2e} fp32 {res['fp32']['rel_err']:.2e}", file=sys.stderr, flush=True)
 
+    c5 = None if args.no_c5 else measure_c5(torch, P, W, dev, max(3, args.steps // 4), 1)
+
     head = "fp32"
     tim = res[head]["timing"]
     dom = max(tim, key=lambda k: tim[k]["ms"])
@@ -260,6 +313,7 @@ def main() -> int:
         "roofline": roofline,
         "apply_roofline_fp32": apply_roofline,
         "cpu_baseline": cpu,
+        "c5_batched": c5,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -2,7 +2,10 @@
 // libbfly.  Not installed; the public interface is include/bfly.h.
 //
 // Weight layout (in place across all levels).  The N^d (A,B) pairs of every
-// level live in N^d slots of r * nrhs complex values ([slot][node][rhs]).
+// level live in N^d slots of r complex values per right-hand side.  The
+// right-hand sides are processed in chunks of RC (the phase factors are
+// shared within a chunk); a chunk's weights are [slot][node][RC], and the
+// chunks follow one another (right-hand side k's chunk starts at k N^d r).
 // Viewing a slot index as L digits of d bits, at level l the low l digits
 // hold the target box A (digit k = the bits of A's (k+1)-th split, coarsest
 // first) and the high L - l digits hold the source box B in Morton order
@@ -35,7 +38,7 @@ struct Geo {
 
 // Device workspace carved into typed pieces (see carve()).
 struct Work {
-  void* W = nullptr;            // weights, one slot per (A,B) pair: [P][r][nrhs] complex
+  void* W = nullptr;            // weights: per chunk of RC right-hand sides [P][r][RC] complex
   uint32_t* keys = nullptr;     // leaf key per input point
   uint32_t* keys_sorted = nullptr;
   int32_t* idx = nullptr;       // 0..n-1
@@ -121,7 +124,7 @@ struct ItemDesc {
   const double* pts_out;
   const int32_t* offs;
   int64_t ld_in, ld_out, n_out;
-  int nrhs;                // right-hand-side stride of W
+  int nrhs;                // right-hand sides of the instance
   int chunks;              // chunks of RC right-hand sides in the range
 };
 
