@@ -188,6 +188,29 @@ def measure_c5(torch, P, W, dev, steps: int, warmup: int) -> dict:
     return out
 
 
+def measure_c4(torch, P, W, dev) -> dict:
+    """The many-right-hand-side Fourier configuration: d = 2, N = 2048, q = 6,
+    64 right-hand sides, one apply per precision (after one warm-up)."""
+    t0 = time.time()
+    w = W.C4()
+    plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+    y, x, g = (torch.from_numpy(a).to(dev) for a in (w.y, w.x, w.g))
+    pts = w.N ** 2 * w.nrhs
+    print(f"[bench] C4: {w.N ** 2} points x {w.nrhs} rhs ({time.time() - t0:.1f}s to generate)", file=sys.stderr,
+          flush=True)
+    out = {"workload": "Fourier phase on uniform grids, d=2, N=2048, q=6 (r=36), 64 right-hand sides",
+           "points_x_rhs": pts, "unit": "Mpoints/s"}
+    for prec in ("fp32", "fp64"):
+        ws = plan.workspace(w.y.shape[0], w.nrhs, prec, device=dev)
+        f = torch.empty_like(g)
+        ms = time_steps(lambda: plan.apply(y, g, x, prec, out=f, workspace=ws), torch, 1, 1)
+        out[prec] = {"ms": round(ms, 2), "value": round(pts / ms / 1e3, 3)}
+        print(f"[bench] C4 {prec}: {ms:.1f} ms -> {pts / ms / 1e3:.1f} Mpoints/s", file=sys.stderr, flush=True)
+        del ws, f
+        torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +219,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (no rel err either)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (default: all in affinity)")
     ap.add_argument("--no-c5", action="store_true", help="skip the batched 48-instance measurement")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 64-right-hand-side Fourier measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one plain device copy of 1 GiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -269,6 +293,7 @@ def main() -> int:
               f"{res['fp64']['rel_err']:.2e} fp32 {res['fp32']['rel_err']:.2e}", file=sys.stderr, flush=True)
 
     c5 = None if args.no_c5 else measure_c5(torch, P, W, dev, max(3, args.steps // 4), 1)
+    c4 = None if args.no_c4 else measure_c4(torch, P, W, dev)
 
     head = "fp32"
     tim = res[head]["timing"]
@@ -314,6 +339,7 @@ def main() -> int:
         "apply_roofline_fp32": apply_roofline,
         "cpu_baseline": cpu,
         "c5_batched": c5,
+        "c4_many_rhs": c4,
     }
     print(json.dumps(out), flush=True)
     return 0
