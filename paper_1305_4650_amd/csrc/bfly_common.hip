@@ -23,14 +23,28 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Sort of the leaf keys: rocPRIM's radix_sort_pairs restricted to its merge
-// sort algorithm at every size.  Its onesweep algorithm (the default above
-// 1 Mi keys) clears scratch with hipMemsetAsync, and memset nodes in a
-// captured graph are avoided here; the merge sort launches kernels only.
-// (MI355X, 1 Mi 20-bit keys: 0.16 ms for the whole binning; onesweep 0.13.)
-// The same configuration sizes the scratch in sort_storage_bytes.
-using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
-                                              rocprim::default_config, ~size_t(0)>;
+// Sort of the leaf keys (stable, so both configurations give the same
+// permutation): rocPRIM's radix_sort_pairs with its onesweep algorithm
+// above 64 Ki keys when the stream is not being captured, and restricted to
+// its merge sort when it is (onesweep clears scratch with hipMemsetAsync,
+// and memset nodes in a captured graph are avoided here; the merge sort
+// launches kernels only).  MI355X, 1 Mi 20-bit keys: the whole binning takes
+// 0.13 ms with onesweep, 0.16 ms with the merge sort.
+using SortFast = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                            rocprim::default_config, 65536>;
+using SortMerge = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                             rocprim::default_config, ~size_t(0)>;
+
+hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint32_t* keys, uint32_t* keys_out, const int32_t* vals,
+                      int32_t* vals_out, unsigned n, int bits, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) return e;
+  size_t b = tmp_bytes;
+  if (cs == hipStreamCaptureStatusNone)
+    return rocprim::radix_sort_pairs<SortFast>(tmp, b, keys, keys_out, vals, vals_out, n, 0, bits, st);
+  return rocprim::radix_sort_pairs<SortMerge>(tmp, b, keys, keys_out, vals, vals_out, n, 0, bits, st);
+}
 
 // leaf index along one dimension: floor((v - lo) / extent * n), clamped to
 // [0, n-1]; NaN goes to 0
@@ -100,9 +114,8 @@ hipError_t bin_sources(const Geo& G, int64_t n_in, const double* pts_in, const W
   if (n_in > 0) {
     k_bin<D><<<blocks_for(n_in), kBlock, 0, st>>>(G, n_in, pts_in, w.keys, w.idx);
     if (D * G.L > 0) {
-      size_t tmp = w.sort_tmp_bytes;
-      const hipError_t e = rocprim::radix_sort_pairs<SortConfig>(w.sort_tmp, tmp, w.keys, w.keys_sorted, w.idx, w.perm,
-                                                     (unsigned)n_in, 0, D * G.L, st);
+      const hipError_t e =
+          sort_pairs(w.sort_tmp, w.sort_tmp_bytes, w.keys, w.keys_sorted, w.idx, w.perm, (unsigned)n_in, D * G.L, st);
       if (e != hipSuccess) return e;
     } else {
       k_iota<<<blocks_for(n_in), kBlock, 0, st>>>(n_in, w.perm, w.keys_sorted);
@@ -214,9 +227,8 @@ hipError_t bin_batch(const BinInst* bi, int n, int64_t n_total, uint64_t leaves_
     int bits = 0;
     while (bits < 32 && ((uint64_t)1 << bits) < leaves_total) ++bits;
     if (bits > 0) {
-      size_t tmp = w.sort_tmp_bytes;
-      const hipError_t e = rocprim::radix_sort_pairs<SortConfig>(w.sort_tmp, tmp, w.keys, w.keys_sorted, w.idx,
-                                                                 w.perm, (unsigned)n_total, 0, bits, st);
+      const hipError_t e =
+          sort_pairs(w.sort_tmp, w.sort_tmp_bytes, w.keys, w.keys_sorted, w.idx, w.perm, (unsigned)n_total, bits, st);
       if (e != hipSuccess) return e;
     } else {
       k_iota<<<blocks_for(n_total), kBlock, 0, st>>>(n_total, w.perm, w.keys_sorted);
@@ -244,8 +256,15 @@ size_t weight_bytes(const Geo& g, int nrhs, int prec) {
 hipError_t sort_storage_bytes(int64_t n, int bits, size_t* bytes) {
   *bytes = 0;
   if (n <= 0 || bits <= 0) return hipSuccess;
-  return rocprim::radix_sort_pairs<SortConfig>(nullptr, *bytes, (uint32_t*)nullptr, (uint32_t*)nullptr, (int32_t*)nullptr,
-                                   (int32_t*)nullptr, (unsigned)n, 0, bits, (hipStream_t)0);
+  size_t fast = 0, merge = 0;
+  hipError_t e = rocprim::radix_sort_pairs<SortFast>(nullptr, fast, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                                     (int32_t*)nullptr, (int32_t*)nullptr, (unsigned)n, 0, bits,
+                                                     (hipStream_t)0);
+  if (e != hipSuccess) return e;
+  e = rocprim::radix_sort_pairs<SortMerge>(nullptr, merge, (uint32_t*)nullptr, (uint32_t*)nullptr, (int32_t*)nullptr,
+                                           (int32_t*)nullptr, (unsigned)n, 0, bits, (hipStream_t)0);
+  *bytes = std::max(fast, merge);
+  return e;
 }
 
 hipError_t run_apply(const Geo& g, int prec, int64_t n_in, const double* pts_in, const double* vals_in,
