@@ -96,8 +96,7 @@ int layout(const bfly_plan_s& p, int64_t n_in, int nrhs, int prec, Layout* out) 
   off += up(4 * n);
   L.keys_sorted = off;
   off += up(4 * n);
-  L.idx = off;
-  off += up(4 * n);
+  L.idx = 0;  // the single-apply sort numbers the points itself
   L.perm = off;
   off += up(4 * n);
   L.offs = off;
@@ -150,7 +149,7 @@ int apply_common(bfly_plan_t plan, bool adjoint, int64_t n_in, const double* pin
   w.W = base + L.w;
   w.keys = reinterpret_cast<uint32_t*>(base + L.keys);
   w.keys_sorted = reinterpret_cast<uint32_t*>(base + L.keys_sorted);
-  w.idx = reinterpret_cast<int32_t*>(base + L.idx);
+  w.idx = nullptr;
   w.perm = reinterpret_cast<int32_t*>(base + L.perm);
   w.offs = reinterpret_cast<int32_t*>(base + L.offs);
   w.sort_tmp = base + L.tmp;

@@ -11,8 +11,6 @@
 //                middle switch                                 (bfly_fused.inc)
 //   k_second     row-space merge-and-split stages             (bfly_fused.inc)
 //   k_final      f_AY := U_AY w_AY at every target (Sec. 1)     (bfly_fused.inc)
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include <algorithm>
 #include <cstdlib>
 
@@ -23,27 +21,231 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Sort of the leaf keys (stable, so both configurations give the same
-// permutation): rocPRIM's radix_sort_pairs with its onesweep algorithm
-// above 64 Ki keys when the stream is not being captured, and restricted to
-// its merge sort when it is (onesweep clears scratch with hipMemsetAsync,
-// and memset nodes in a captured graph are avoided here; the merge sort
-// launches kernels only).  MI355X, 1 Mi 20-bit keys: the whole binning takes
-// 0.13 ms with onesweep, 0.16 ms with the merge sort.
-using SortFast = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
-                                            rocprim::default_config, 65536>;
-using SortMerge = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
-                                             rocprim::default_config, ~size_t(0)>;
+// ---- stable LSD radix sort of the 32-bit leaf keys with int32 payloads ----
+// Passes go from the lowest digit (at most kMaxDigit bits) up; each pass is a
+// stable counting sort by its digit, so the passes together give the stable
+// sort by the whole key.  A pass is three launches:
+//   k_digit_hist     digit counts of every tile of kTile keys, stored
+//                    digit-major: cnt[digit * ntile + tile]
+//   k_digit_scan     exclusive prefix of each digit's row over the tiles (in
+//                    place) and the row total tot[digit]
+//   k_digit_scatter  stable rank of each key inside its tile (wave by wave,
+//                    64 keys at a time, lanes of equal digit found by one
+//                    ballot per digit bit), then the write to
+//                    sum(tot below its digit) + row prefix + rank
+// Kernels only (no memset), so a captured graph records launches alone; the
+// permutation is the same on every run.
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortKeys = 16;  // keys per thread
+constexpr int kTile = kSortThreads * kSortKeys;
+constexpr int kMaxDigit = 11;
 
-hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint32_t* keys, uint32_t* keys_out, const int32_t* vals,
-                      int32_t* vals_out, unsigned n, int bits, hipStream_t st) {
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  const hipError_t e = hipStreamIsCapturing(st, &cs);
-  if (e != hipSuccess) return e;
-  size_t b = tmp_bytes;
-  if (cs == hipStreamCaptureStatusNone)
-    return rocprim::radix_sort_pairs<SortFast>(tmp, b, keys, keys_out, vals, vals_out, n, 0, bits, st);
-  return rocprim::radix_sort_pairs<SortMerge>(tmp, b, keys, keys_out, vals, vals_out, n, 0, bits, st);
+struct SortPlan {
+  int passes = 0, width[3] = {0, 0, 0}, shift[3] = {0, 0, 0}, maxw = 0;
+  int ntile = 0;
+};
+
+SortPlan sort_plan(int64_t n, int bits) {
+  SortPlan s;
+  if (n <= 0 || bits <= 0) return s;
+  s.passes = (bits + kMaxDigit - 1) / kMaxDigit;
+  int sh = 0;
+  for (int p = 0; p < s.passes; ++p) {
+    s.width[p] = bits / s.passes + (p < bits % s.passes ? 1 : 0);
+    s.shift[p] = sh;
+    sh += s.width[p];
+    s.maxw = std::max(s.maxw, s.width[p]);
+  }
+  s.ntile = (int)((n + kTile - 1) / kTile);
+  return s;
+}
+
+inline size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// scratch: cnt [2^maxw][ntile], tot [2^maxw], and with two passes or more a
+// second key / payload buffer for the passes to alternate with the output
+size_t sort_bytes(const SortPlan& s, int64_t n) {
+  if (s.passes == 0) return 0;
+  const size_t B = (size_t)1 << s.maxw;
+  size_t b = up256(4 * B * (size_t)s.ntile) + up256(4 * B);
+  if (s.passes > 1) b += 2 * up256(4 * (size_t)n);
+  return b;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                             int nb, int ntile, int32_t* __restrict__ cnt) {
+  __shared__ int32_t h[1 << kMaxDigit];
+  const int B = 1 << nb;
+  for (int i = threadIdx.x; i < B; i += kSortThreads) h[i] = 0;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t e0 = (int64_t)blockIdx.x * kTile + (int64_t)w * 64 * kSortKeys + lane;
+  uint32_t k[kSortKeys];
+#pragma unroll
+  for (int c = 0; c < kSortKeys; ++c) {
+    const int64_t e = e0 + c * 64;
+    k[c] = e < n ? keys[e] : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kSortKeys; ++c)
+    if (e0 + c * 64 < n) atomicAdd(&h[(k[c] >> shift) & (uint32_t)(B - 1)], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < B; i += kSortThreads) cnt[(int64_t)i * ntile + blockIdx.x] = h[i];
+}
+
+// one wave per digit; a lane takes 8 consecutive tiles of the row at a time
+__global__ __launch_bounds__(kSortThreads) void k_digit_scan(int nb, int ntile, int32_t* __restrict__ cnt,
+                                                             int32_t* __restrict__ tot) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int dig = blockIdx.x * kSortWaves + w;
+  if (dig >= (1 << nb)) return;
+  int32_t* row = cnt + (int64_t)dig * ntile;
+  int32_t carry = 0;
+  for (int t0 = 0; t0 < ntile; t0 += 64 * 8) {
+    const int b = t0 + lane * 8;
+    int32_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = b + j < ntile ? row[b + j] : 0;
+    int32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int32_t x = v[j];
+      v[j] = s;
+      s += x;
+    }
+    int32_t incl = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    const int32_t ex = carry + incl - s;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (b + j < ntile) row[b + j] = ex + v[j];
+    carry += __shfl(incl, 63);
+  }
+  if (lane == 0) tot[dig] = carry;
+}
+
+// vals == nullptr: the payload of key e is e
+__global__ __launch_bounds__(kSortThreads) void k_digit_scatter(const uint32_t* __restrict__ keys,
+                                                                const int32_t* __restrict__ vals, int64_t n, int shift,
+                                                                int nb, int ntile, const int32_t* __restrict__ cnt,
+                                                                const int32_t* __restrict__ tot,
+                                                                uint32_t* __restrict__ keys_out,
+                                                                int32_t* __restrict__ vals_out) {
+  __shared__ int32_t h[kSortWaves][1 << kMaxDigit];
+  __shared__ int32_t part[kSortWaves];
+  const int B = 1 << nb;
+  const uint32_t mask = (uint32_t)(B - 1);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t e0 = (int64_t)blockIdx.x * kTile + (int64_t)w * 64 * kSortKeys + lane;
+  uint32_t k[kSortKeys];
+  int32_t v[kSortKeys];
+#pragma unroll
+  for (int c = 0; c < kSortKeys; ++c) {
+    const int64_t e = e0 + c * 64;
+    k[c] = e < n ? keys[e] : 0u;
+    v[c] = e < n ? (vals ? vals[e] : (int32_t)e) : 0;
+  }
+  // every wave counts its own 64 * kSortKeys keys in its own row of h
+  for (int i = lane; i < B; i += 64) h[w][i] = 0;
+  const uint64_t lower = (1ull << lane) - 1ull;
+  int32_t r[kSortKeys];
+#pragma unroll
+  for (int c = 0; c < kSortKeys; ++c) {
+    const bool ok = e0 + c * 64 < n;
+    const uint32_t d = (k[c] >> shift) & mask;
+    uint64_t peers = __ballot(ok);
+    for (int b = 0; b < nb; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t set = __ballot(bit);
+      peers &= bit ? set : ~set;
+    }
+    r[c] = 0;
+    if (ok) {
+      // all lanes of the digit read the count before the lowest of them
+      // (the leader) adds the group's size: one wave, LDS in program order
+      const int32_t before = h[w][d];
+      r[c] = before + __popcll(peers & lower);
+      if ((peers & lower) == 0ull) h[w][d] = before + __popcll(peers);
+    }
+  }
+  // digit bases: tot summed below the digit + this tile's row prefix, and
+  // per wave the counts of the waves before it
+  const int per = (B + kSortThreads - 1) / kSortThreads;
+  const int d0 = threadIdx.x * per;
+  int32_t s = 0;
+  for (int j = 0; j < per; ++j)
+    if (d0 + j < B) s += tot[d0 + j];
+  int32_t incl = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) part[w] = incl;
+  __syncthreads();
+  int32_t base = incl - s;
+  for (int ww = 0; ww < w; ++ww) base += part[ww];
+  for (int j = 0; j < per; ++j) {
+    const int dd = d0 + j;
+    if (dd < B) {
+      int32_t acc = base + cnt[(int64_t)dd * ntile + blockIdx.x];
+      base += tot[dd];
+#pragma unroll
+      for (int ww = 0; ww < kSortWaves; ++ww) {
+        const int32_t x = h[ww][dd];
+        h[ww][dd] = acc;
+        acc += x;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kSortKeys; ++c) {
+    if (e0 + c * 64 < n) {
+      const int64_t dst = (int64_t)h[w][(k[c] >> shift) & mask] + r[c];
+      if (dst >= 0 && dst < n) {
+        keys_out[dst] = k[c];
+        vals_out[dst] = v[c];
+      }
+    }
+  }
+}
+
+// Stable sort of (keys, vals) by the low `bits` bits of the keys into
+// (keys_out, vals_out); vals == nullptr stands for vals[e] = e.  n >= 1,
+// 1 <= bits <= 32, tmp of sort_bytes(sort_plan(n, bits), n) bytes.
+hipError_t radix_sort(const uint32_t* keys, const int32_t* vals, int64_t n, int bits, uint32_t* keys_out,
+                      int32_t* vals_out, void* tmp, size_t tmp_bytes, hipStream_t st) {
+  const SortPlan s = sort_plan(n, bits);
+  if (s.passes == 0 || tmp_bytes < sort_bytes(s, n)) return hipErrorInvalidValue;
+  const size_t B = (size_t)1 << s.maxw;
+  char* p = static_cast<char*>(tmp);
+  int32_t* cnt = reinterpret_cast<int32_t*>(p);
+  p += up256(4 * B * (size_t)s.ntile);
+  int32_t* tot = reinterpret_cast<int32_t*>(p);
+  p += up256(4 * B);
+  uint32_t* k_alt = reinterpret_cast<uint32_t*>(p);
+  int32_t* v_alt = reinterpret_cast<int32_t*>(p + up256(4 * (size_t)n));
+  const uint32_t* kin = keys;
+  const int32_t* vin = vals;
+  for (int pass = 0; pass < s.passes; ++pass) {
+    // the last pass writes the output; earlier ones alternate with it
+    const bool to_out = ((s.passes - 1 - pass) & 1) == 0;
+    uint32_t* ko = to_out ? keys_out : k_alt;
+    int32_t* vo = to_out ? vals_out : v_alt;
+    const int nb = s.width[pass];
+    k_digit_hist<<<s.ntile, kSortThreads, 0, st>>>(kin, n, s.shift[pass], nb, s.ntile, cnt);
+    k_digit_scan<<<((1 << nb) + kSortWaves - 1) / kSortWaves, kSortThreads, 0, st>>>(nb, s.ntile, cnt, tot);
+    k_digit_scatter<<<s.ntile, kSortThreads, 0, st>>>(kin, vin, n, s.shift[pass], nb, s.ntile, cnt, tot, ko, vo);
+    kin = ko;
+    vin = vo;
+  }
+  return hipGetLastError();
 }
 
 // leaf index along one dimension: floor((v - lo) / extent * n), clamped to
@@ -68,7 +270,7 @@ __device__ __forceinline__ uint32_t morton(const int64_t* b, int ndig) {
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_bin(const Geo G, int64_t n, const double* __restrict__ pts,
-                                                uint32_t* __restrict__ keys, int32_t* __restrict__ idx) {
+                                                uint32_t* __restrict__ keys) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int64_t b[3];
@@ -76,7 +278,6 @@ __global__ __launch_bounds__(kBlock) void k_bin(const Geo G, int64_t n, const do
 #pragma unroll
   for (int j = 0; j < D; ++j) b[j] = bin1(pts[i * D + j], G.slo[j], G.sD[j], N);
   keys[i] = morton<D>(b, G.L);
-  idx[i] = (int32_t)i;
 }
 
 // offs[m] = first sorted position whose key is >= m, for m = 0..P
@@ -112,10 +313,10 @@ hipError_t bin_sources(const Geo& G, int64_t n_in, const double* pts_in, const W
   const int64_t P = (int64_t)1 << (D * G.L);
   StepTimer tb(kStepBin, st);
   if (n_in > 0) {
-    k_bin<D><<<blocks_for(n_in), kBlock, 0, st>>>(G, n_in, pts_in, w.keys, w.idx);
+    k_bin<D><<<blocks_for(n_in), kBlock, 0, st>>>(G, n_in, pts_in, w.keys);
     if (D * G.L > 0) {
       const hipError_t e =
-          sort_pairs(w.sort_tmp, w.sort_tmp_bytes, w.keys, w.keys_sorted, w.idx, w.perm, (unsigned)n_in, D * G.L, st);
+          radix_sort(w.keys, nullptr, n_in, D * G.L, w.keys_sorted, w.perm, w.sort_tmp, w.sort_tmp_bytes, st);
       if (e != hipSuccess) return e;
     } else {
       k_iota<<<blocks_for(n_in), kBlock, 0, st>>>(n_in, w.perm, w.keys_sorted);
@@ -228,7 +429,7 @@ hipError_t bin_batch(const BinInst* bi, int n, int64_t n_total, uint64_t leaves_
     while (bits < 32 && ((uint64_t)1 << bits) < leaves_total) ++bits;
     if (bits > 0) {
       const hipError_t e =
-          sort_pairs(w.sort_tmp, w.sort_tmp_bytes, w.keys, w.keys_sorted, w.idx, w.perm, (unsigned)n_total, bits, st);
+          radix_sort(w.keys, w.idx, n_total, bits, w.keys_sorted, w.perm, w.sort_tmp, w.sort_tmp_bytes, st);
       if (e != hipSuccess) return e;
     } else {
       k_iota<<<blocks_for(n_total), kBlock, 0, st>>>(n_total, w.perm, w.keys_sorted);
@@ -254,17 +455,8 @@ size_t weight_bytes(const Geo& g, int nrhs, int prec) {
 }
 
 hipError_t sort_storage_bytes(int64_t n, int bits, size_t* bytes) {
-  *bytes = 0;
-  if (n <= 0 || bits <= 0) return hipSuccess;
-  size_t fast = 0, merge = 0;
-  hipError_t e = rocprim::radix_sort_pairs<SortFast>(nullptr, fast, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                                     (int32_t*)nullptr, (int32_t*)nullptr, (unsigned)n, 0, bits,
-                                                     (hipStream_t)0);
-  if (e != hipSuccess) return e;
-  e = rocprim::radix_sort_pairs<SortMerge>(nullptr, merge, (uint32_t*)nullptr, (uint32_t*)nullptr, (int32_t*)nullptr,
-                                           (int32_t*)nullptr, (unsigned)n, 0, bits, (hipStream_t)0);
-  *bytes = std::max(fast, merge);
-  return e;
+  *bytes = sort_bytes(sort_plan(n, bits), n);
+  return hipSuccess;
 }
 
 hipError_t run_apply(const Geo& g, int prec, int64_t n_in, const double* pts_in, const double* vals_in,

@@ -41,7 +41,7 @@ struct Work {
   void* W = nullptr;            // weights: per chunk of RC right-hand sides [P][r][RC] complex
   uint32_t* keys = nullptr;     // leaf key per input point
   uint32_t* keys_sorted = nullptr;
-  int32_t* idx = nullptr;       // 0..n-1
+  int32_t* idx = nullptr;       // batched: index of each point inside its instance
   int32_t* perm = nullptr;      // input points sorted by leaf (stable)
   int32_t* offs = nullptr;      // CSR offsets per leaf, P + 1
   void* sort_tmp = nullptr;
@@ -70,7 +70,7 @@ void timing_set(bool on);
 
 // Bytes of weight storage for one apply.
 size_t weight_bytes(const Geo& g, int nrhs, int prec);
-// Bytes of scratch the device radix sort needs for n keys of `bits` bits.
+// Bytes of scratch the leaf-key radix sort needs for n keys of `bits` bits.
 hipError_t sort_storage_bytes(int64_t n, int bits, size_t* bytes);
 
 // Everything the level kernels of one apply need (after binning).
