@@ -89,7 +89,7 @@ struct LevelArgs {
   int64_t ld_out = 0;
   hipStream_t stream = nullptr;
   int ub_force = 0;              // fusion units per workgroup block (0: chosen per launch)
-  int k_fuse = 2;                // merge-and-split stages fused per launch (at most)
+  int k_fuse = 0;                // merge-and-split stages fused per launch, at most (0: by shape)
   size_t lds_budget = 81920;     // bytes of LDS per workgroup (two workgroups per CU)
 };
 hipError_t run_levels_d1(const LevelArgs& la, int prec);
@@ -135,7 +135,7 @@ struct BatchGroup {
   const int32_t* perm = nullptr;  // all instances' input points sorted by (instance, leaf)
   ItemDesc* desc = nullptr;       // device room for 2 n descriptors
   hipStream_t stream = nullptr;
-  int k_fuse = 2;
+  int k_fuse = 0;
   size_t lds_budget = 81920;
   int ub_force = 0;
 };
