@@ -21,7 +21,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-PHASES = {"fourier": 0, "hypradon2": 1, "genradon3": 2, "separable": 3}
+PHASES = {"fourier": 0, "hypradon2": 1, "genradon3": 2, "separable": 3, "genradon3pi": 4}
 
 _CFLAGS = ["-O3", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
            "-std=c11", "-D_DEFAULT_SOURCE", "-Wall"]

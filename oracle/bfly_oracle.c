@@ -77,6 +77,19 @@ double orc_tau(int phase, int d, long N, const double* x, const double* y) {
       double dot = (x[0] * y[0] + x[1] * y[1]) + x[2] * y[2];
       return Nd * (dot + sqrt(s));
     }
+    case ORC_GENRADON3_PI: { /* generalized-Radon analogue (Sec. 3.2) as the paper
+                                prints it: Phi = pi (x.p + sqrt(gamma^2 + kappa^2)),
+                                gamma = p0 g0(x), kappa = p1 g1(x); no N inside */
+      double u0 = TWO_PI * x[0];
+      double u1 = TWO_PI * x[1];
+      double g0 = (2.0 + sin(u0) * sin(u1)) / 3.0;
+      double g1 = (2.0 + cos(u0) * cos(u1)) / 3.0;
+      double t0 = g0 * y[0];
+      double t1 = g1 * y[1];
+      double s = t0 * t0 + t1 * t1;
+      double dot = (x[0] * y[0] + x[1] * y[1]) + x[2] * y[2];
+      return 0.5 * (dot + sqrt(s));
+    }
     case ORC_SEPARABLE: { /* additively separable test phase: K has rank one */
       double a = 0.0, b = 0.0;
       for (int j = 0; j < d; ++j) {
@@ -227,8 +240,8 @@ static int setup(prob* p, int d, long N, int q, int phase,
   if (q < 1 || q > ORC_QMAX) return 1;
   if (nrhs < 1 || nrhs > 64) return 1;
   if (phase == ORC_HYPRADON2 && d != 2) return 1;
-  if (phase == ORC_GENRADON3 && d != 3) return 1;
-  if (phase < 0 || phase > 3) return 1;
+  if ((phase == ORC_GENRADON3 || phase == ORC_GENRADON3_PI) && d != 3) return 1;
+  if (phase < 0 || phase > 4) return 1;
   memset(p, 0, sizeof(*p));
   p->d = d;
   p->N = N;

@@ -23,6 +23,8 @@ extern "C" {
 #define ORC_HYPRADON2 1 /* tau = N x0 sqrt(y0^2 + x1^2 y1^2)                     d=2 */
 #define ORC_GENRADON3 2 /* tau = N (x.y + sqrt(g0(x)^2 y0^2 + g1(x)^2 y1^2 + y2^2)) d=3 */
 #define ORC_SEPARABLE 3 /* tau = N (sum_j x_j^2 + sum_j y_j^3)                    */
+#define ORC_GENRADON3_PI 4 /* tau = (x.p + sqrt(gamma^2 + kappa^2)) / 2, gamma = p0 g0(x),
+                              kappa = p1 g1(x): Phi = pi (...) exactly as printed, d=3 */
 
 /* tau(x, y) of the forward kernel (test access to the phase definitions). */
 double orc_tau(int phase, int d, long N, const double* x, const double* y);

@@ -20,7 +20,7 @@ BFLY_OK, BFLY_EINVAL, BFLY_EUNSUPPORTED, BFLY_ENOMEM, BFLY_EDEVICE, BFLY_EWORKSP
 BFLY_PHASE_FOURIER, BFLY_PHASE_HYPRADON2, BFLY_PHASE_GENRADON3, BFLY_PHASE_SEPARABLE_TEST = range(4)
 BFLY_FP64, BFLY_FP32 = 0, 1
 
-PHASES = {"fourier": 0, "hypradon2": 1, "genradon3": 2, "separable": 3}
+PHASES = {"fourier": 0, "hypradon2": 1, "genradon3": 2, "separable": 3, "genradon3pi": 4}
 PRECISIONS = {"fp64": BFLY_FP64, "fp32": BFLY_FP32}
 
 EXPORTS = ("bfly_plan", "bfly_plan_destroy", "bfly_plan_info", "bfly_workspace_size", "bfly_apply",

@@ -22,7 +22,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-PHASE_IDS = {"fourier": 0, "hypradon2": 1, "genradon3": 2, "separable": 3}
+PHASE_IDS = {"fourier": 0, "hypradon2": 1, "genradon3": 2, "separable": 3, "genradon3pi": 4}
 SEED_BASE = 13054650
 
 
@@ -127,6 +127,22 @@ def genradon3(N: int, q: int = 4, nrhs: int = 1, config_id: int = 3,
     g = random_rhs(rng(config_id, 1), nrhs, N ** d)
     return Workload(name or f"genradon3_N{N}_q{q}", d, N, q, "genradon3",
                     lo, hi, lo.copy(), hi.copy(), y, x, g, config_id)
+
+
+def genradon3pi(N: int, q: int = 5, nrhs: int = 1, config_id: int = 6,
+                name: str | None = None) -> Workload:
+    """The generalized-Radon analogue exactly as the paper prints it (no N in
+    the phase): targets x = k/N on [0,1)^3, sources p jittered on the
+    frequency box [-N/2, N/2)^3."""
+    d = 3
+    tlo, thi = np.zeros(3), np.ones(3)
+    slo, shi = np.full(3, -N / 2.0), np.full(3, N / 2.0)
+    jit = rng(config_id, 0).random((N ** d, d))
+    y = grid_points(N, slo, shi, jitter=jit)
+    x = grid_points(N, tlo, thi)
+    g = random_rhs(rng(config_id, 1), nrhs, N ** d)
+    return Workload(name or f"genradon3pi_N{N}_q{q}", d, N, q, "genradon3pi",
+                    slo, shi, tlo, thi, y, x, g, config_id)
 
 
 def separable(N: int, d: int = 2, q: int = 3, nrhs: int = 1, config_id: int = 9) -> Workload:

@@ -92,11 +92,12 @@ def test_direct_sum_plane_wave_geometric_series(orc):
         assert np.abs(f - ref).max() < 1e-10 * N ** d
 
 
-@pytest.mark.parametrize("phase", ["hypradon2", "genradon3", "fourier", "separable"])
+@pytest.mark.parametrize("phase", ["hypradon2", "genradon3", "fourier", "separable", "genradon3pi"])
 def test_direct_sum_delta_source(orc, phase):
     """g = delta at y_j0 gives f(x) = exp(i Phi(x, y_j0)) at every target."""
     mk = {"hypradon2": lambda: W.hypradon2(8), "genradon3": lambda: W.genradon3(4),
-          "fourier": lambda: W.fourier_grid(8), "separable": lambda: W.separable(8)}[phase]
+          "fourier": lambda: W.fourier_grid(8), "separable": lambda: W.separable(8),
+          "genradon3pi": lambda: W.genradon3pi(4)}[phase]
     w = mk()
     j0 = 5
     g = np.zeros(w.y.shape[0], complex)
@@ -107,16 +108,35 @@ def test_direct_sum_delta_source(orc, phase):
     assert np.abs(f - ref).max() < 1e-15
 
 
-@pytest.mark.parametrize("phase", ["hypradon2", "genradon3"])
+@pytest.mark.parametrize("phase", ["hypradon2", "genradon3", "genradon3pi"])
 def test_direct_sum_adjoint_identity(orc, phase):
     """<K g, f> = <g, K^H f>: pins the sign and the role swap of the adjoint."""
-    w = W.hypradon2(8) if phase == "hypradon2" else W.genradon3(4)
+    w = {"hypradon2": lambda: W.hypradon2(8), "genradon3": lambda: W.genradon3(4),
+         "genradon3pi": lambda: W.genradon3pi(4)}[phase]()
     fvec = W.random_rhs(W.rng(77, 1), 1, w.x.shape[0])
     Kg = orc.direct(phase, w.N, w.y, w.g, w.x)
     KHf = orc.direct(phase, w.N, w.x, fvec, w.y, adjoint=True)
     lhs = np.vdot(fvec, Kg)
     rhs = np.vdot(KHf, w.g)
     assert abs(lhs - rhs) < 1e-13 * abs(lhs) * 10
+
+
+def test_genradon3pi_axis_sources_are_half_frequency_sum(orc):
+    """Sources on the p2 axis (p0 = p1 = 0) make gamma = kappa = 0, so the
+    printed phase pi (x.p + sqrt(gamma^2 + kappa^2)) is pi x2 p2: with p2 =
+    j - N/2, x2 = k/N and g = 1 the sum is a geometric series in
+    w = exp(i pi k / N), the same for every x0, x1.  Pins the factor pi (not
+    2 pi) and the x.p term."""
+    N = 8
+    p2 = np.arange(N, dtype=float) - N / 2
+    y = np.stack([np.zeros(N), np.zeros(N), p2], axis=1)
+    gen = W.rng(61, 0)
+    k = np.arange(1, 2 * N, dtype=float)  # k = 0 and 2N would make w = 1
+    x = np.stack([gen.random(k.size), gen.random(k.size), k / N], axis=1)
+    f = orc.direct("genradon3pi", N, y, np.ones((1, N), complex), x)[0]
+    w = np.exp(1j * np.pi * k / N)
+    ref = np.exp(-1j * np.pi * k / 2) * (1 - w ** N) / (1 - w)
+    assert np.abs(f - ref).max() < 1e-12
 
 
 def test_hypradon_row_reduces_to_1d_dft(orc):
@@ -205,7 +225,8 @@ def _cheb_interp_eval(vals, pts_ref):
     return out
 
 
-@pytest.mark.parametrize("phase,d,q", [("hypradon2", 2, 4), ("fourier", 1, 6), ("fourier", 2, 3)])
+@pytest.mark.parametrize("phase,d,q", [("hypradon2", 2, 4), ("fourier", 1, 6), ("fourier", 2, 3),
+                                     ("genradon3pi", 3, 3)])
 def test_butterfly_N1_is_two_sided_chebyshev_interpolation(orc, phase, d, q):
     """With N = 1 there are no stages: init, switch, final.  The result is the
     kernel exp(i(Phi(x,c_Y) + Phi(c_X,y))) times the two-sided tensor
@@ -282,6 +303,30 @@ def test_butterfly_genradon_error_decreases(orc):
         fd = orc.direct(w.phase, w.N, w.y, w.g, w.x)
         errs.append(rel(fb, fd))
     assert np.all(np.diff(errs) < 0), errs
+
+
+def test_butterfly_genradon3pi_error_decreases(orc):
+    """The printed generalized-Radon phase has its square-root cone at p0 = p1
+    = 0, inside the source box: convergence in q is slow but monotone."""
+    errs = []
+    for q in (2, 3, 4, 5, 6):
+        w = W.genradon3pi(4, q=q)
+        fb = orc.butterfly(w.phase, w.N, q, w.src_box, w.tgt_box, w.y, w.g, w.x)
+        fd = orc.direct(w.phase, w.N, w.y, w.g, w.x)
+        errs.append(rel(fb, fd))
+    assert np.all(np.diff(errs) < 0), errs
+
+
+def test_butterfly_genradon3pi_matches_stated_accuracy(orc):
+    """Sec. 3.2 chooses r = 5^3 for roughly one percent relative error in the
+    supremum norm.  With the printed phase, q = 5 and N = 16 the oracle's
+    sup-norm error relative to max |f| lies between 0.5% and 3% (1.9%); the
+    phase at twice or half its scale, or a dropped term, leaves that band."""
+    w = W.genradon3pi(16, q=5)
+    fb = orc.butterfly(w.phase, w.N, 5, w.src_box, w.tgt_box, w.y, w.g, w.x)
+    fd = orc.direct(w.phase, w.N, w.y, w.g, w.x)
+    e = np.abs(fb - fd).max() / np.abs(fd).max()
+    assert 5e-3 < e < 3e-2, e
 
 
 def test_butterfly_linearity(orc):
