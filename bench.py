@@ -30,6 +30,7 @@ PEAK_VALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, non-p
 # Flops charged per evaluation of tau (sqrt, sin and cos as below), see the design doc.
 SINCOS_FLOPS = 28  # sin + cos pair of a reduced argument (two Horner polynomials)
 TAU_FLOPS = {"fourier": lambda d: 2 * d - 1, "hypradon2": lambda d: 6, "genradon3": lambda d: 80,
+             "genradon3pi": lambda d: 78,
              "separable": lambda d: 5 * d}
 
 

@@ -67,12 +67,17 @@ enum {
  *               g0 = (2 + sin 2pi x0 sin 2pi x1)/3,
  *               g1 = (2 + cos 2pi x0 cos 2pi x1)/3           d = 3  (Sec. 3.2 family)
  *  SEPARABLE_TEST tau = N (sum_j x_j^2 + sum_j y_j^3)        any d  (rank-one kernel:
- *               the butterfly is exact, used to check results at any size) */
+ *               the butterfly is exact, used to check results at any size)
+ *  GENRADON3_PI tau = (x.p + sqrt(gamma^2 + kappa^2)) / 2, gamma = p0 g0(x),
+ *               kappa = p1 g1(x) with g0, g1 as above: the Sec. 3.2 phase as
+ *               printed, Phi = pi (...), no N inside (the scale comes from the
+ *               source box, e.g. p in [-N/2, N/2)^3)          d = 3 */
 enum {
   BFLY_PHASE_FOURIER = 0,
   BFLY_PHASE_HYPRADON2 = 1,
   BFLY_PHASE_GENRADON3 = 2,
-  BFLY_PHASE_SEPARABLE_TEST = 3
+  BFLY_PHASE_SEPARABLE_TEST = 3,
+  BFLY_PHASE_GENRADON3_PI = 4
 };
 
 /* precision modes (internal arithmetic; I/O is always complex128)

@@ -319,9 +319,11 @@ int bfly_plan(int d, int64_t N, const double* src_lo, const double* src_hi, cons
     if (!std::isfinite(tgt_lo[j]) || !std::isfinite(tgt_hi[j]) || !(tgt_hi[j] > tgt_lo[j]))
       return fail(BFLY_EINVAL, "target box must be finite with hi > lo in every dimension");
   }
-  if (phase_id < 0 || phase_id > 3) return fail(BFLY_EINVAL, "unknown phase id %d", phase_id);
+  if (phase_id < 0 || phase_id > 4) return fail(BFLY_EINVAL, "unknown phase id %d", phase_id);
   if (phase_id == BFLY_PHASE_HYPRADON2 && d != 2) return fail(BFLY_EUNSUPPORTED, "HYPRADON2 needs d = 2");
   if (phase_id == BFLY_PHASE_GENRADON3 && d != 3) return fail(BFLY_EUNSUPPORTED, "GENRADON3 needs d = 3");
+  if (phase_id == BFLY_PHASE_GENRADON3_PI && d != 3)
+    return fail(BFLY_EUNSUPPORTED, "GENRADON3_PI needs d = 3");
   bfly_plan_s* p = new (std::nothrow) bfly_plan_s;
   if (!p) return fail(BFLY_ENOMEM, "plan allocation failed");
   p->d = d;

@@ -63,6 +63,9 @@ def plan_rc(d, N, sbox, tbox, phase, q):
     ((2, 64, BOX2, TBOX2, 7, 5), B.BFLY_EINVAL),                      # unknown phase
     ((3, 8, (np.zeros(3), np.ones(3)), (np.zeros(3), np.ones(3)), 1, 4), B.BFLY_EUNSUPPORTED),
     ((2, 8, BOX2, TBOX2, 2, 4), B.BFLY_EUNSUPPORTED),
+    ((2, 8, BOX2, TBOX2, 4, 4), B.BFLY_EUNSUPPORTED),                 # GENRADON3_PI needs d = 3
+    ((2, 64, BOX2, TBOX2, 5, 5), B.BFLY_EINVAL),                      # unknown phase
+    ((3, 8, (np.full(3, -4.0), np.full(3, 4.0)), (np.zeros(3), np.ones(3)), 4, 5), B.BFLY_OK),
     ((1, 1, (np.zeros(1), np.ones(1)), (np.zeros(1), np.ones(1)), 0, 16), B.BFLY_OK),
 ])
 def test_plan_validation(args, code):
