@@ -212,6 +212,30 @@ def measure_c4(torch, P, W, dev) -> dict:
     return out
 
 
+def measure_3d(torch, P, W, dev, steps: int) -> dict:
+    """The 3-D generalized-Radon configurations: the workload form (N = 64,
+    q = 4, r = 64) and the phase as printed (N = 64, q = 5, r = 125), one
+    right-hand side, timed per precision over a few applies."""
+    out = {"unit": "Mpoints/s"}
+    for key, w, what in (
+            ("c3_genradon3", W.C3(), "3-D generalized-Radon analogue N (x.y + sqrt(...)), N=64, q=4 (r=64)"),
+            ("genradon3pi", W.genradon3pi(64, q=5), "3-D generalized Radon as printed, pi (x.p + sqrt(...)), "
+                                                     "N=64, q=5 (r=125), p in [-32, 32)^3")):
+        plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+        y, x, g = (torch.from_numpy(a).to(dev) for a in (w.y, w.x, w.g))
+        pts = w.N ** 3 * w.nrhs
+        rec = {"workload": what, "points": pts}
+        for prec in ("fp32", "fp64"):
+            ws = plan.workspace(w.y.shape[0], w.nrhs, prec, device=dev)
+            f = torch.empty_like(g)
+            ms = time_steps(lambda: plan.apply(y, g, x, prec, out=f, workspace=ws), torch, steps, 2)
+            rec[prec] = {"ms": round(ms, 3), "value": round(pts / ms / 1e3, 3)}
+            print(f"[bench] {key} {prec}: {ms:.2f} ms -> {pts / ms / 1e3:.1f} Mpoints/s", file=sys.stderr,
+                  flush=True)
+        out[key] = rec
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +245,7 @@ def main() -> int:
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (default: all in affinity)")
     ap.add_argument("--no-c5", action="store_true", help="skip the batched 48-instance measurement")
     ap.add_argument("--no-c4", action="store_true", help="skip the 64-right-hand-side Fourier measurement")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D generalized-Radon measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one plain device copy of 1 GiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -295,6 +320,7 @@ def main() -> int:
 
     c5 = None if args.no_c5 else measure_c5(torch, P, W, dev, max(3, args.steps // 4), 1)
     c4 = None if args.no_c4 else measure_c4(torch, P, W, dev)
+    r3d = None if args.no_3d else measure_3d(torch, P, W, dev, 5)
 
     head = "fp32"
     tim = res[head]["timing"]
@@ -341,6 +367,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "c5_batched": c5,
         "c4_many_rhs": c4,
+        "genradon_3d": r3d,
     }
     print(json.dumps(out), flush=True)
     return 0
