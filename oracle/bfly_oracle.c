@@ -254,7 +254,9 @@ static int setup(prob* p, int d, long N, int q, int phase,
   p->phase = phase;
   p->adj = adjoint ? 1 : 0;
   p->nrhs = nrhs;
-  p->ls = switch_level < 0 ? p->L / 2 : switch_level;
+  /* middle switch level (Sec. 1.4): floor(L/2) forward; the adjoint runs its
+     levels in the mirror order of the forward's, so its middle is L - floor(L/2) */
+  p->ls = switch_level < 0 ? (adjoint ? p->L - p->L / 2 : p->L / 2) : switch_level;
   if (p->ls > p->L) return 1;
   /* the adjoint swaps the roles of the two boxes */
   const double *sl = adjoint ? tlo : slo, *sh = adjoint ? thi : shi;

@@ -49,7 +49,10 @@ int orc_direct(int phase, int d, long N, int adjoint,
  * [tlo, thi), f = B g.  Adjoint (adjoint=1): the same plan geometry, but
  * the swapped problem is run: sources are the x points (box [tlo,thi)),
  * targets are the y points, phase -Phi(x, y).
- * switch_level < 0 selects floor(L/2).
+ * switch_level < 0 selects the middle level: floor(L/2) forward, and
+ * L - floor(L/2) for the adjoint, which is then the exact transpose of the
+ * forward butterfly (its stages are the forward's transposed, level for
+ * level, once the switch sits at the forward switch's mirror level).
  * counts (may be NULL) receives [phase evaluations, real x complex MACs per
  * RHS, switch complex MACs per RHS, stages run].  1 <= nrhs <= 64. */
 int orc_butterfly(int d, long N, int q, int phase,

@@ -329,6 +329,26 @@ def test_butterfly_genradon3pi_matches_stated_accuracy(orc):
     assert 5e-3 < e < 3e-2, e
 
 
+@pytest.mark.parametrize("mk", [
+    lambda: W.hypradon2(8, q=3), lambda: W.hypradon2(32, q=4), lambda: W.hypradon2(16, q=3),
+    lambda: W.fourier_grid(32, d=1, q=5), lambda: W.fourier_grid(2, d=2, q=4), lambda: W.genradon3(8, q=2),
+    lambda: W.genradon3pi(2, q=3), lambda: W.hypradon2(1, q=4)])
+def test_butterfly_adjoint_is_exact_transpose(orc, mk):
+    """<B g, f> = <g, B' f> to rounding for the butterfly B and the adjoint
+    butterfly B' at odd and even L (N = 1 ... 32): with the adjoint's switch
+    at L - floor(L/2) every step of B' is the transpose of a step of B (in
+    the demodulated variables), so B' = B^H exactly, not only up to the
+    interpolation error.  Any transposed table, wrong node, sign or
+    modulation centre in either direction breaks the identity at O(1)."""
+    w = mk()
+    fvec = W.random_rhs(W.rng(w.config_id, 2), 1, w.x.shape[0])
+    Bg = orc.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, w.y, w.g, w.x)
+    Bf = orc.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, w.x, fvec, w.y, adjoint=True)
+    lhs, rhs = np.vdot(fvec, Bg), np.vdot(Bf, w.g)
+    scale = np.linalg.norm(fvec) * np.linalg.norm(Bg)
+    assert abs(lhs - rhs) < 1e-14 * scale, (lhs, rhs)
+
+
 def test_butterfly_linearity(orc):
     w = W.hypradon2(16, q=4, nrhs=2)
     a, b = 0.3 - 1.2j, 2.5 + 0.1j
