@@ -103,7 +103,8 @@ int bfly_plan(int d, int64_t N, const double* src_lo, const double* src_hi,
 /* Destroy a plan (NULL is accepted).  Returns BFLY_OK. */
 int bfly_plan_destroy(bfly_plan_t plan);
 
-/* Query a plan: out[0..4] = d, N, q, r = q^d, switch level floor(log2 N / 2).
+/* Query a plan: out[0..4] = d, N, q, r = q^d, switch level floor(log2 N / 2)
+ * of the forward apply (the adjoint switches at log2 N minus that).
  * Returns BFLY_OK or BFLY_EINVAL. */
 int bfly_plan_info(bfly_plan_t plan, int64_t* out5);
 
@@ -135,7 +136,10 @@ int bfly_apply(bfly_plan_t plan,
  * kernel K^H(y, x) = exp(-i Phi(x, y)): the same steps with the roles of
  * the two point sets swapped and the phase negated (Sec. 1: the low-rank
  * condition is symmetric in diam(A) diam(B)).  B' approximates K^H to the
- * same accuracy; it is not the exact transpose of B.
+ * same accuracy.  Its middle switch sits at level L - floor(L/2), the mirror
+ * of the forward apply's floor(L/2) (Sec. 1.4), so each of its steps is the
+ * transpose of a step of B and B' = B^H exactly (up to rounding): gradients
+ * through B computed with B' are exact for the computed forward.
  *  n_tgt, x       the plan's targets (now the inputs), device double[n_tgt][d]
  *  f_in, ldf      device complex128 [nrhs][ldf], ldf >= n_tgt
  *  n_src, y       the plan's sources (now the outputs), device double[n_src][d]

@@ -57,7 +57,9 @@ bfly::Geo make_geo(const bfly_plan_s& p, bool adjoint) {
   g.L = p.L;
   g.q = p.q;
   g.r = p.r;
-  g.ls = p.L / 2;
+  // middle switch (Sec. 1.4); the adjoint's levels mirror the forward's, so
+  // its switch at L - floor(L/2) makes it the exact transpose of the forward
+  g.ls = adjoint ? p.L - p.L / 2 : p.L / 2;
   g.phase = p.phase;
   g.adj = adjoint ? 1 : 0;
   g.nc = 1 << p.d;
