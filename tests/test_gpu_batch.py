@@ -143,3 +143,40 @@ def test_c5_batch_equals_single_applies(prec):
         torch.cuda.synchronize()
         assert torch.equal(outs[k], single), f"instance {k} (N={plan.N})"
     del outs
+
+
+def _instances_other_dims():
+    """d = 1 and d = 3 groups beside a d = 2 one: Fourier 1-D (forward and
+    adjoint), the 3-D generalized-Radon workload form (right-hand-side chunks
+    and a remainder), the printed 3-D phase, and a 3-D adjoint."""
+    return [
+        (W.fourier_grid(64, d=1, q=8, nrhs=2, config_id=930), False),
+        (W.fourier_grid(16, d=1, q=5, nrhs=1, config_id=931), True),
+        (W.genradon3(8, q=4, nrhs=3, config_id=932), False),
+        (W.genradon3pi(4, q=5, config_id=933), False),
+        (W.separable(4, d=3, q=2, config_id=934), True),
+        (W.hypradon2(8, q=5, nrhs=1, config_id=935), False),
+    ]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_other_dims_equal_single_and_oracle(orc, prec):
+    """Batched groups for d = 1 and d = 3: each instance equals its own apply
+    bit for bit, and (FP64) the oracle to 1e-12."""
+    insts = _instances_other_dims()
+    items = _items(insts, np.random.default_rng(12))
+    print(f"[case] batched d = 1, 2, 3 mix, {prec}", flush=True)
+    outs = P.apply_batched(items, prec)
+    torch.cuda.synchronize()
+    for k, ((w, adj), (plan, _, pin, vin, pout)) in enumerate(zip(insts, items)):
+        single = plan.apply_adjoint(pin, vin, pout, prec) if adj else plan.apply(pin, vin, pout, prec)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[k], single), f"instance {k} (d={w.d}, N={w.N}, adjoint={adj})"
+        if prec == "fp64":
+            v = vin.cpu().numpy()
+            ref = (orc.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, w.x, v, w.y, adjoint=True) if adj
+                   else orc.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, w.y, v, w.x))
+            got = outs[k].cpu().numpy()
+            e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            print(f"  instance {k} d={w.d} N={w.N} adjoint={adj}: rel err {e:.3e}", flush=True)
+            assert e < 1e-12, k
