@@ -139,6 +139,32 @@ def time_steps(fn, torch, steps: int, warmup: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
+def time_each(fn, torch, n: int) -> dict:
+    """n applies timed one by one with HIP events on the current stream:
+    median and interquartile range in ms."""
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    q1, med, q3 = np.percentile(t, [25, 50, 75])
+    return {"n": n, "median_ms": round(float(med), 4), "iqr_ms": round(float(q3 - q1), 4)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def measure_c5(torch, P, W, dev, steps: int, warmup: int) -> dict:
     """The uneven batch: 48 hyperbolic-Radon instances (N from {128, 256,
     512, 1024}, q = 5, 8 right-hand sides) in one batched apply, eagerly and
@@ -289,6 +315,7 @@ def main() -> int:
             plan.apply(y, g, x, prec, out=f, workspace=ws)
 
         ms = time_steps(step, torch, args.steps, args.warmup)
+        dist = time_each(step, torch, 20)
         # instrumented pass: per-step-kind HIP event timing on the apply's stream
         P.bfly_timing_enable(True)
         P.bfly_timing_read()
@@ -297,7 +324,7 @@ def main() -> int:
         torch.cuda.synchronize()
         tim = P.bfly_timing_read()
         P.bfly_timing_enable(False)
-        res[prec] = {"ms": ms, "out": f.cpu().numpy(), "timing": tim}
+        res[prec] = {"ms": ms, "out": f.cpu().numpy(), "timing": tim, "dist": dist}
         print(f"[bench] {prec}: {ms:.3f} ms/apply  {npts / ms / 1e3:.1f} Mpoints/s  "
               + " ".join(f"{k}={v['ms'] / args.steps:.3f}ms/{v['launches'] // args.steps}"
                          for k, v in tim.items()), file=sys.stderr, flush=True)
@@ -307,12 +334,23 @@ def main() -> int:
     if not args.no_cpu_baseline:
         import oracle
         cores = args.cpu_threads or len(os.sched_getaffinity(0))
+        runs = []
+        for _ in range(3):
+            t0 = time.time()
+            ref = oracle.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, w.y, w.g, w.x, nthreads=cores)
+            runs.append(time.time() - t0)
+        t_cpu = float(np.median(runs))
+        # one thread on a smaller sample of the same geometry (N = 256)
+        ws1 = W.hypradon2(256, q=w.q, config_id=2)
         t0 = time.time()
-        ref = oracle.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, w.y, w.g, w.x, nthreads=cores)
-        t_cpu = time.time() - t0
+        oracle.butterfly(ws1.phase, ws1.N, ws1.q, ws1.src_box, ws1.tgt_box, ws1.y, ws1.g, ws1.x, nthreads=1)
+        t_one = time.time() - t0
         cpu = {"value": npts / t_cpu / 1e6, "unit": "Mpoints/s", "cores": cores, "kind": "oracle",
-               "sample": "the full workload: one FP64 oracle butterfly apply of all 1,048,576 sources "
-                         f"and targets ({t_cpu:.1f} s)"}
+               "sample": "the full workload: FP64 oracle butterfly applies of all 1,048,576 sources and targets, "
+                         f"median of 3 ({', '.join(f'{t:.1f}' for t in runs)} s)",
+               "cpu_model": cpu_model(),
+               "single_thread": {"value": round(ws1.N ** 2 / t_one / 1e6, 4), "unit": "Mpoints/s",
+                                 "sample": f"same geometry at N = 256 (65,536 points), 1 thread ({t_one:.1f} s)"}}
         for prec in res:
             res[prec]["rel_err"] = rel(res[prec]["out"], ref)
         print(f"[bench] oracle {t_cpu:.1f}s on {cores} threads; rel err fp64 "
@@ -359,7 +397,8 @@ def main() -> int:
                    "contraction_unit": "valu"},
         "rel_err_vs_oracle": res[head].get("rel_err"),
         "fp64": {"value": round(npts / res["fp64"]["ms"] / 1e3, 3), "ms_per_step": round(res["fp64"]["ms"], 4),
-                 "rel_err_vs_oracle": res["fp64"].get("rel_err")},
+                 "rel_err_vs_oracle": res["fp64"].get("rel_err"), "per_apply": res["fp64"]["dist"]},
+        "per_apply": res[head]["dist"],
         "speedup_fp32_over_fp64": round(res["fp64"]["ms"] / res[head]["ms"], 3),
         "launch_ms": {p: {k: round(v["ms"] / args.steps, 5) for k, v in res[p]["timing"].items()} for p in res},
         "roofline": roofline,

@@ -180,3 +180,50 @@ def test_batched_other_dims_equal_single_and_oracle(orc, prec):
             e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
             print(f"  instance {k} d={w.d} N={w.N} adjoint={adj}: rel err {e:.3e}", flush=True)
             assert e < 1e-12, k
+
+
+def test_c5_gradient_matches_finite_differences():
+    """The least-squares problem at its real shape: 4 C5 instances (N from
+    {128, ..., 1024}, q = 5, 8 right-hand sides), data d = B g_true + 1%
+    complex Gaussian noise (scaled by the rms of B g_true), loss
+    1/2 sum ||B g - d||^2 at g_0 ~ N(0,1) + iN(0,1), gradient from the batched
+    autograd function (backward: one batched adjoint apply, which is B^H).
+    Central differences on 16 seeded coordinates x {re, im} per instance; the
+    loss is quadratic in g, so they are exact for any step and h = 1 keeps
+    the difference far above the rounding of a loss of order 1e12."""
+    sizes = W.C5_sizes()[:4]
+    insts = [W.C5_instance(i, int(N)) for i, N in enumerate(sizes)]
+    spec, gs, ds = [], [], []
+    for w in insts:
+        plan = _plan(w)
+        y, x = _dev(w.y), _dev(w.x)
+        f_true = plan.apply(y, _dev(w.g), x, "fp64")
+        rms = float(f_true.abs().pow(2).mean().sqrt())
+        noise = W.random_rhs(W.rng(w.config_id, 2), w.nrhs, w.x.shape[0]) / np.sqrt(2.0)
+        ds.append(f_true + _dev(0.01 * rms * noise))
+        spec.append((plan, y, x))
+        gs.append(_dev(W.random_rhs(W.rng(w.config_id, 3), w.nrhs, w.y.shape[0])).requires_grad_(True))
+    print(f"[case] C5 finite differences, N = {list(map(int, sizes))}", flush=True)
+    fs = P.bfly_apply_batched_autograd(gs, spec, "fp64")
+    sum(0.5 * (f - d).abs().pow(2).sum() for f, d in zip(fs, ds)).backward()
+    h = 1.0
+    for k, ((plan, y, x), g, d, w) in enumerate(zip(spec, gs, ds, insts)):
+        grad = g.grad.cpu().numpy()
+        g0 = g.detach()
+
+        def loss(gv):
+            return 0.5 * float((plan.apply(y, gv, x, "fp64") - d).abs().pow(2).sum())
+
+        coords = W.rng(w.config_id, 3).integers(0, [w.nrhs, w.y.shape[0]], size=(16, 2))
+        err = 0.0
+        for (rr, j) in coords:
+            fd = 0.0 + 0.0j
+            for unit in (1.0, 1j):
+                gp, gm = g0.clone(), g0.clone()
+                gp[rr, j] += h * unit
+                gm[rr, j] -= h * unit
+                fd += unit * (loss(gp) - loss(gm)) / (2 * h)
+            err = max(err, abs(fd - grad[rr, j]))
+        scale = np.abs(grad).max()
+        print(f"  instance {k} N={w.N}: fd max err / max|grad| = {err / scale:.3e}", flush=True)
+        assert err / scale < 1e-7, k
