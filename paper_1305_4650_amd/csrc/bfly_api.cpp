@@ -102,7 +102,7 @@ int layout(const bfly_plan_s& p, int64_t n_in, int nrhs, int prec, Layout* out) 
   L.perm = off;
   off += up(4 * n);
   L.offs = off;
-  off += up(4 * (P + 1));
+  off += up(4 * (P + 2));  // offsets, then the empty-leaf flag
   L.tmp = off;
   off += up(tmp_bytes);
   L.total = off;
@@ -154,6 +154,7 @@ int apply_common(bfly_plan_t plan, bool adjoint, int64_t n_in, const double* pin
   w.idx = nullptr;
   w.perm = reinterpret_cast<int32_t*>(base + L.perm);
   w.offs = reinterpret_cast<int32_t*>(base + L.offs);
+  w.empty = w.offs + ((int64_t)1 << (plan->d * plan->L)) + 1;
   w.sort_tmp = base + L.tmp;
   w.sort_tmp_bytes = L.tmp_bytes;
   bfly::Geo g = make_geo(*plan, adjoint);
@@ -218,7 +219,7 @@ int batch_layout(int n, const bfly_batch_item* items, int prec, BLayout* out) {
   L.perm = off;
   off += up(4 * nt);
   L.offs = off;
-  off += up(4 * (L.leaves + 1));
+  off += up(4 * (L.leaves + 2));  // offsets, then the empty-leaf flag
   L.desc = off;
   off += up(2 * (size_t)n * sizeof(bfly::ItemDesc));
   L.tmp = off;
@@ -244,6 +245,7 @@ int apply_batched(int n, const bfly_batch_item* items, int prec, void* ws, size_
   w.idx = reinterpret_cast<int32_t*>(base + L.idx);
   w.perm = reinterpret_cast<int32_t*>(base + L.perm);
   w.offs = reinterpret_cast<int32_t*>(base + L.offs);
+  w.empty = w.offs + L.leaves + 1;
   w.sort_tmp = base + L.tmp;
   w.sort_tmp_bytes = L.tmp_bytes;
   std::vector<bfly::Geo> geo(n);
@@ -289,6 +291,7 @@ int apply_batched(int n, const bfly_batch_item* items, int prec, void* ws, size_
     bg.inst = grp.data();
     bg.n = (int)grp.size();
     bg.perm = w.perm;
+    bg.empty = w.empty;
     bg.desc = reinterpret_cast<bfly::ItemDesc*>(base + L.desc) + desc_next;
     bg.stream = st;
     bfly::tune_batch_from_env(bg);

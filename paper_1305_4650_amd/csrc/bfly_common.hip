@@ -270,8 +270,9 @@ __device__ __forceinline__ uint32_t morton(const int64_t* b, int ndig) {
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_bin(const Geo G, int64_t n, const double* __restrict__ pts,
-                                                uint32_t* __restrict__ keys) {
+                                                uint32_t* __restrict__ keys, int32_t* __restrict__ empty) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *empty = 0;  // k_offsets, launched after this kernel, sets it for an empty leaf
   if (i >= n) return;
   int64_t b[3];
   const int64_t N = (int64_t)1 << G.L;
@@ -280,20 +281,52 @@ __global__ __launch_bounds__(kBlock) void k_bin(const Geo G, int64_t n, const do
   keys[i] = morton<D>(b, G.L);
 }
 
-// offs[m] = first sorted position whose key is >= m, for m = 0..P
+// offs[m] = first sorted position whose key is >= m, for m = 0..P: one
+// thread per m.  The search starts at m n / P (exact when every leaf holds
+// one point), gallops away from it and finishes by bisection, so a leaf costs
+// O(1) loads for evenly spread points and O(log n) however sparse they are.
+// A leaf m < P without points (its first key >= m is not m) sets *empty = 1
+// (with no points at all every leaf does, the flag needing no clearing).
 __global__ __launch_bounds__(kBlock) void k_offsets(int64_t n, int64_t P, const uint32_t* __restrict__ ks,
-                                                    int32_t* __restrict__ offs) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n == 0) {
-    for (int64_t m = k; m <= P; m += (int64_t)gridDim.x * blockDim.x) offs[m] = 0;
-    return;
+                                                    int32_t* __restrict__ offs, int32_t* __restrict__ empty) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m > P) return;
+  const int64_t g = P > 0 ? m * n / P : 0;  // m <= 2^30, n < 2^31: no overflow
+  int64_t lo, hi;
+  if (g < n && (int64_t)ks[g] < m) {  // the answer lies above g
+    lo = g + 1;
+    hi = n;
+    for (int64_t step = 1;; step <<= 1) {
+      const int64_t p = lo + step - 1;
+      if (p >= n) break;
+      if ((int64_t)ks[p] >= m) {
+        hi = p;
+        break;
+      }
+      lo = p + 1;
+    }
+  } else {  // the answer is at most g (g = n included)
+    hi = g < n ? g : n;
+    lo = 0;
+    for (int64_t step = 1;; step <<= 1) {
+      const int64_t p = hi - step;
+      if (p < 0) break;
+      if ((int64_t)ks[p] < m) {
+        lo = p + 1;
+        break;
+      }
+      hi = p;
+    }
   }
-  if (k >= n) return;
-  const int64_t prev = k == 0 ? -1 : (int64_t)ks[k - 1];
-  const int64_t cur = ks[k];
-  for (int64_t m = prev + 1; m <= cur; ++m) offs[m] = (int32_t)k;
-  if (k == n - 1)
-    for (int64_t m = cur + 1; m <= P; ++m) offs[m] = (int32_t)n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)ks[mid] < m)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  offs[m] = (int32_t)lo;
+  if (m < P && (lo == n || (int64_t)ks[lo] != m)) *empty = 1;
 }
 
 // N = 1: every point is in the single leaf
@@ -313,7 +346,7 @@ hipError_t bin_sources(const Geo& G, int64_t n_in, const double* pts_in, const W
   const int64_t P = (int64_t)1 << (D * G.L);
   StepTimer tb(kStepBin, st);
   if (n_in > 0) {
-    k_bin<D><<<blocks_for(n_in), kBlock, 0, st>>>(G, n_in, pts_in, w.keys);
+    k_bin<D><<<blocks_for(n_in), kBlock, 0, st>>>(G, n_in, pts_in, w.keys, w.empty);
     if (D * G.L > 0) {
       const hipError_t e =
           radix_sort(w.keys, nullptr, n_in, D * G.L, w.keys_sorted, w.perm, w.sort_tmp, w.sort_tmp_bytes, st);
@@ -321,10 +354,8 @@ hipError_t bin_sources(const Geo& G, int64_t n_in, const double* pts_in, const W
     } else {
       k_iota<<<blocks_for(n_in), kBlock, 0, st>>>(n_in, w.perm, w.keys_sorted);
     }
-    k_offsets<<<blocks_for(n_in), kBlock, 0, st>>>(n_in, P, w.keys_sorted, w.offs);
-  } else {
-    k_offsets<<<blocks_for(P + 1), kBlock, 0, st>>>(0, P, nullptr, w.offs);
   }
+  k_offsets<<<blocks_for(P + 1), kBlock, 0, st>>>(n_in, P, w.keys_sorted, w.offs, w.empty);
   return hipGetLastError();
 }
 
@@ -343,8 +374,10 @@ struct BinArgs {
 };
 
 __global__ __launch_bounds__(kBlock) void k_bin_batch(const BinArgs a, int64_t g0, int64_t g1,
-                                                      uint32_t* __restrict__ keys, int32_t* __restrict__ idx) {
+                                                      uint32_t* __restrict__ keys, int32_t* __restrict__ idx,
+                                                      int32_t* __restrict__ empty) {
   const int64_t g = g0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) *empty = 0;  // k_offsets, launched after this kernel, sets it for an empty leaf
   if (g >= g1) return;
   int k = 0;
   while (k + 1 < a.n && a.it[k + 1].pbase <= g) ++k;
@@ -422,7 +455,7 @@ hipError_t bin_batch(const BinInst* bi, int n, int64_t n_total, uint64_t leaves_
       }
       pbase += b.n;
     }
-    if (pbase > g0) k_bin_batch<<<blocks_for(pbase - g0), kBlock, 0, st>>>(a, g0, pbase, w.keys, w.idx);
+    if (pbase > g0) k_bin_batch<<<blocks_for(pbase - g0), kBlock, 0, st>>>(a, g0, pbase, w.keys, w.idx, w.empty);
   }
   if (n_total > 0) {
     int bits = 0;
@@ -434,10 +467,9 @@ hipError_t bin_batch(const BinInst* bi, int n, int64_t n_total, uint64_t leaves_
     } else {
       k_iota<<<blocks_for(n_total), kBlock, 0, st>>>(n_total, w.perm, w.keys_sorted);
     }
-    k_offsets<<<blocks_for(n_total), kBlock, 0, st>>>(n_total, (int64_t)leaves_total, w.keys_sorted, w.offs);
-  } else {
-    k_offsets<<<blocks_for((int64_t)leaves_total + 1), kBlock, 0, st>>>(0, (int64_t)leaves_total, nullptr, w.offs);
   }
+  k_offsets<<<blocks_for((int64_t)leaves_total + 1), kBlock, 0, st>>>(n_total, (int64_t)leaves_total,
+                                                                      w.keys_sorted, w.offs, w.empty);
   return hipGetLastError();
 }
 
@@ -475,6 +507,7 @@ hipError_t run_apply(const Geo& g, int prec, int64_t n_in, const double* pts_in,
   la.ld_in = ld_in;
   la.perm = w.perm;
   la.offs = w.offs;
+  la.empty = w.empty;
   la.n_out = n_out;
   la.pts_out = pts_out;
   la.vals_out = vals_out;

@@ -44,6 +44,7 @@ struct Work {
   int32_t* idx = nullptr;       // batched: index of each point inside its instance
   int32_t* perm = nullptr;      // input points sorted by leaf (stable)
   int32_t* offs = nullptr;      // CSR offsets per leaf, P + 1
+  int32_t* empty = nullptr;     // set by binning: 1 if some leaf holds no input point
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
 };
@@ -83,6 +84,7 @@ struct LevelArgs {
   int64_t ld_in = 0;
   const int32_t* perm = nullptr;
   const int32_t* offs = nullptr;
+  const int32_t* empty = nullptr;  // device flag: 1 if some leaf holds no input point
   int64_t n_out = 0;
   const double* pts_out = nullptr;
   double* vals_out = nullptr;
@@ -133,6 +135,7 @@ struct BatchGroup {
   const BatchInst* inst = nullptr;
   int n = 0;
   const int32_t* perm = nullptr;  // all instances' input points sorted by (instance, leaf)
+  const int32_t* empty = nullptr; // device flag: 1 if some leaf of some instance holds no point
   ItemDesc* desc = nullptr;       // device room for 2 n descriptors
   hipStream_t stream = nullptr;
   int k_fuse = 0;

@@ -145,6 +145,31 @@ def genradon3pi(N: int, q: int = 5, nrhs: int = 1, config_id: int = 6,
                     slo, shi, tlo, thi, y, x, g, config_id)
 
 
+def hypradon2_curve(N: int, q: int = 5, nrhs: int = 1, config_id: int = 7, per_leaf_row: int = 4,
+                    curve_targets: bool = False, name: str | None = None) -> Workload:
+    """Sparse points: the hyperbolic-Radon geometry with per_leaf_row * N
+    sources on the curve y = (1 + u, 0.5 + 0.4 sin 2 pi u), u uniform on
+    [0, 1) (so O(N) of the N^2 source leaves hold points), targets x = k/N on
+    the full grid.  curve_targets puts the curve on the target side instead
+    (x = (u, 0.5 + 0.4 sin 2 pi u)) with grid sources, the sparse input of an
+    adjoint apply."""
+    d = 2
+    slo, shi = np.array([1.0, 0.0]), np.array([2.0, 1.0])
+    tlo, thi = np.zeros(2), np.ones(2)
+    u = np.sort(rng(config_id, 0).random(per_leaf_row * N))
+    curve = np.stack([u, 0.5 + 0.4 * np.sin(2 * np.pi * u)], axis=1)
+    if curve_targets:
+        y = grid_points(N, slo, shi, jitter=rng(config_id, 3).random((N ** d, d)))
+        x = np.ascontiguousarray(curve)
+    else:
+        y = np.ascontiguousarray(curve + np.array([1.0, 0.0]))
+        x = grid_points(N, tlo, thi)
+    g = random_rhs(rng(config_id, 1), nrhs, y.shape[0])
+    kind = "tgtcurve" if curve_targets else "srccurve"
+    return Workload(name or f"hypradon2_{kind}_N{N}_q{q}", d, N, q, "hypradon2",
+                    slo, shi, tlo, thi, y, x, g, config_id)
+
+
 def separable(N: int, d: int = 2, q: int = 3, nrhs: int = 1, config_id: int = 9) -> Workload:
     """Separable test phase tau = N (|x|^2 + sum y^3) on jittered unit grids."""
     lo, hi = np.zeros(d), np.ones(d)
