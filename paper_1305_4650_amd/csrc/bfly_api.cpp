@@ -79,7 +79,7 @@ bfly::Geo make_geo(const bfly_plan_s& p, bool adjoint) {
 }
 
 struct Layout {
-  size_t w, keys, keys_sorted, idx, perm, offs, tmp, total;
+  size_t w, keys, keys_sorted, idx, perm, offs, tocc, tmp, total;
   size_t tmp_bytes;
 };
 
@@ -103,6 +103,8 @@ int layout(const bfly_plan_s& p, int64_t n_in, int nrhs, int prec, Layout* out) 
   off += up(4 * n);
   L.offs = off;
   off += up(4 * (P + 2));  // offsets, then the empty-leaf flag
+  L.tocc = off;
+  off += up(bfly::tocc_bytes(p.d, p.L));
   L.tmp = off;
   off += up(tmp_bytes);
   L.total = off;
@@ -155,6 +157,7 @@ int apply_common(bfly_plan_t plan, bool adjoint, int64_t n_in, const double* pin
   w.perm = reinterpret_cast<int32_t*>(base + L.perm);
   w.offs = reinterpret_cast<int32_t*>(base + L.offs);
   w.empty = w.offs + ((int64_t)1 << (plan->d * plan->L)) + 1;
+  w.tocc = reinterpret_cast<uint8_t*>(base + L.tocc);
   w.sort_tmp = base + L.tmp;
   w.sort_tmp_bytes = L.tmp_bytes;
   bfly::Geo g = make_geo(*plan, adjoint);

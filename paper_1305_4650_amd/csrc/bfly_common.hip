@@ -329,6 +329,39 @@ __global__ __launch_bounds__(kBlock) void k_offsets(int64_t n, int64_t P, const 
   if (m < P && (lo == n || (int64_t)ks[lo] != m)) *empty = 1;
 }
 
+// ---- target-box occupancy (sparse targets) ----
+__host__ __device__ inline int64_t tocc_base(int D, int l) { return (((int64_t)1 << (D * l)) - 1) / ((1 << D) - 1); }
+
+__global__ __launch_bounds__(kBlock) void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// every target marks the boxes that contain it on every level 0..L (its
+// leaf as the final evaluation computes it)
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_mark_targets(const Geo G, int64_t n, const double* __restrict__ pts,
+                                                         uint8_t* __restrict__ occ) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t N = (int64_t)1 << G.L;
+  int64_t b[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double u = ((pts[i * D + d] - G.tlo[d]) / G.tD[d]) * (double)N;
+    int64_t v = 0;
+    if (u >= 0.0) v = u >= (double)N ? N - 1 : (int64_t)floor(u);
+    b[d] = v > N - 1 ? N - 1 : v;
+  }
+  for (int l = 0; l <= G.L; ++l) {
+    uint32_t m = 0;
+    for (int k = 0; k < l; ++k)
+#pragma unroll
+      for (int d = 0; d < D; ++d) m |= (uint32_t)(((b[d] >> (G.L - l)) >> k) & 1) << (D * k + d);
+    occ[tocc_base(D, l) + m] = 1;
+  }
+}
+
 // N = 1: every point is in the single leaf
 __global__ __launch_bounds__(kBlock) void k_iota(int64_t n, int32_t* __restrict__ perm,
                                                  uint32_t* __restrict__ keys) {
@@ -491,6 +524,11 @@ hipError_t sort_storage_bytes(int64_t n, int bits, size_t* bytes) {
   return hipSuccess;
 }
 
+size_t tocc_bytes(int d, int L) {
+  const size_t b = (size_t)tocc_base(d, L + 1);
+  return (b + 3) & ~(size_t)3;
+}
+
 hipError_t run_apply(const Geo& g, int prec, int64_t n_in, const double* pts_in, const double* vals_in,
                      int64_t ld_in, int64_t n_out, const double* pts_out, double* vals_out, int64_t ld_out,
                      int nrhs, const Work& w, hipStream_t st) {
@@ -508,6 +546,23 @@ hipError_t run_apply(const Geo& g, int prec, int64_t n_in, const double* pts_in,
   la.perm = w.perm;
   la.offs = w.offs;
   la.empty = w.empty;
+  // fewer targets than leaves: some target boxes are empty on the last
+  // levels, and the level kernels skip units whose target box is empty
+  const int64_t P = (int64_t)1 << (g.d * g.L);
+  if (n_out < P && w.tocc) {
+    const int64_t words = (int64_t)(tocc_bytes(g.d, g.L) / 4);
+    k_zero_words<<<(unsigned)std::min<int64_t>(blocks_for(words), 4096), kBlock, 0, st>>>(
+        reinterpret_cast<uint32_t*>(w.tocc), words);
+    if (n_out > 0) {
+      if (g.d == 1)
+        k_mark_targets<1><<<blocks_for(n_out), kBlock, 0, st>>>(g, n_out, pts_out, w.tocc);
+      else if (g.d == 2)
+        k_mark_targets<2><<<blocks_for(n_out), kBlock, 0, st>>>(g, n_out, pts_out, w.tocc);
+      else
+        k_mark_targets<3><<<blocks_for(n_out), kBlock, 0, st>>>(g, n_out, pts_out, w.tocc);
+    }
+    la.tocc = w.tocc;
+  }
   la.n_out = n_out;
   la.pts_out = pts_out;
   la.vals_out = vals_out;

@@ -45,6 +45,7 @@ struct Work {
   int32_t* perm = nullptr;      // input points sorted by leaf (stable)
   int32_t* offs = nullptr;      // CSR offsets per leaf, P + 1
   int32_t* empty = nullptr;     // set by binning: 1 if some leaf holds no input point
+  uint8_t* tocc = nullptr;      // target-box occupancy, levels 0..L (see tocc_bytes)
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
 };
@@ -71,6 +72,10 @@ void timing_set(bool on);
 
 // Bytes of weight storage for one apply.
 size_t weight_bytes(const Geo& g, int nrhs, int prec);
+// Bytes of the target-box occupancy pyramid (levels 0..L, 2^(d l) boxes at
+// level l, one byte each, stored by level, a box at the Morton index of its
+// l-digit index), rounded up to whole words.
+size_t tocc_bytes(int d, int L);
 // Bytes of scratch the leaf-key radix sort needs for n keys of `bits` bits.
 hipError_t sort_storage_bytes(int64_t n, int bits, size_t* bytes);
 
@@ -85,6 +90,7 @@ struct LevelArgs {
   const int32_t* perm = nullptr;
   const int32_t* offs = nullptr;
   const int32_t* empty = nullptr;  // device flag: 1 if some leaf holds no input point
+  const uint8_t* tocc = nullptr;   // target-box occupancy when targets are sparse, else null
   int64_t n_out = 0;
   const double* pts_out = nullptr;
   double* vals_out = nullptr;

@@ -73,8 +73,9 @@ SMALL = {
     # the generalized-Radon phase as printed (r = 5^3, sources on [-N/2, N/2)^3)
     "genradon3pi_N8_q5": lambda: W.genradon3pi(8, q=5),
     "genradon3pi_N16_q4_2rhs": lambda: W.genradon3pi(16, q=4, nrhs=2),
-    # sparse inputs: sources on a curve (blocks of empty source boxes skip
-    # their work), and the curve on the target side (sparse adjoint inputs)
+    # sparse sets: sources on a curve (blocks of empty source boxes skip
+    # their work), and targets on the curve (blocks of empty target boxes
+    # skip theirs; in the adjoint these are the sparse inputs)
     "srccurve_N64_q5_2rhs": lambda: W.hypradon2_curve(64, q=5, nrhs=2),
     "tgtcurve_N64_q5": lambda: W.hypradon2_curve(64, q=5, curve_targets=True),
 }
@@ -108,7 +109,8 @@ def test_fp64_adjoint_parity(torch_dev, orc, name):
 
 @pytest.mark.parametrize("name", ["C1_fourier2d_N64_q5", "hypradon2_N128_q5", "genradon3_N16_q4_2rhs",
                                   "fourier1d_N64_q8", "hypradon2_N32_q5_9rhs", "fourier2d_N32_q6_9rhs",
-                                  "genradon3pi_N8_q5", "genradon3pi_N16_q4_2rhs", "srccurve_N64_q5_2rhs"])
+                                  "genradon3pi_N8_q5", "genradon3pi_N16_q4_2rhs", "srccurve_N64_q5_2rhs",
+                                  "tgtcurve_N64_q5"])
 def test_fp32_forward_parity(torch_dev, orc, name):
     w = SMALL[name]()
     print(f"[case] fp32 forward {name}", flush=True)
