@@ -297,6 +297,7 @@ def main() -> int:
     ap.add_argument("--no-c5", action="store_true", help="skip the batched 48-instance measurement")
     ap.add_argument("--no-c4", action="store_true", help="skip the 64-right-hand-side Fourier measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D generalized-Radon measurements")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the sparse source / target measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one plain device copy of 1 GiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -384,7 +385,7 @@ def main() -> int:
     c5 = None if args.no_c5 else measure_c5(torch, P, W, dev, max(3, args.steps // 4), 1)
     c4 = None if args.no_c4 else measure_c4(torch, P, W, dev)
     r3d = None if args.no_3d else measure_3d(torch, P, W, dev, 5)
-    sparse = measure_sparse(torch, P, W, dev, 10)
+    sparse = None if args.no_sparse else measure_sparse(torch, P, W, dev, 10)
 
     head = "fp32"
     tim = res[head]["timing"]
