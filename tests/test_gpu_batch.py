@@ -156,6 +156,10 @@ def _instances_other_dims():
         (W.genradon3pi(4, q=5, config_id=933), False),
         (W.separable(4, d=3, q=2, config_id=934), True),
         (W.hypradon2(8, q=5, nrhs=1, config_id=935), False),
+        # sparse sources (blocks of empty source boxes skip their work in the
+        # batched launches too) and sparse targets (computed in full there)
+        (W.hypradon2_curve(32, q=5, nrhs=2, config_id=936), False),
+        (W.hypradon2_curve(32, q=5, config_id=937, curve_targets=True), False),
     ]
 
 
