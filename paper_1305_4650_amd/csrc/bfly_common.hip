@@ -13,6 +13,8 @@
 //   k_final      f_AY := U_AY w_AY at every target (Sec. 1)     (bfly_fused.inc)
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
+#include <vector>
 
 #include "bfly_internal.h"
 
@@ -451,6 +453,21 @@ void tune_from_env(LevelArgs& la) {
   if (ub >= 1 && ub <= 64) la.ub_force = ub;
   if (kf >= 1 && kf <= 8) la.k_fuse = kf;
   if (lds >= 16384 && lds <= 163840) la.lds_budget = (size_t)lds;
+  // BFLY_KSPLIT=a,b,...: stages per launch for a tuning sweep
+  static const std::vector<int> split = [] {
+    std::vector<int> v;
+    const char* e = getenv("BFLY_KSPLIT");
+    for (const char* c = e; c && *c;) {
+      const int k = atoi(c);
+      if (k < 1 || k > 8 || v.size() >= 16) return std::vector<int>();
+      v.push_back(k);
+      c = strchr(c, ',');
+      if (c) ++c;
+    }
+    return v;
+  }();
+  la.nsplit = (int)split.size();
+  for (int i = 0; i < la.nsplit; ++i) la.split[i] = split[i];
 }
 
 }  // namespace

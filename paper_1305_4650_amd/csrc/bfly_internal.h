@@ -98,6 +98,10 @@ struct LevelArgs {
   hipStream_t stream = nullptr;
   int ub_force = 0;              // fusion units per workgroup block (0: chosen per launch)
   int k_fuse = 0;                // merge-and-split stages fused per launch, at most (0: by shape)
+  // tuning override: stages of each launch, column-space launches then
+  // row-space ones (used only when they add up to each half and fit the LDS)
+  int split[16] = {0};
+  int nsplit = 0;
   size_t lds_budget = 81920;     // bytes of LDS per workgroup (two workgroups per CU)
 };
 hipError_t run_levels_d1(const LevelArgs& la, int prec);
