@@ -238,6 +238,39 @@ def measure_c4(torch, P, W, dev) -> dict:
     return out
 
 
+def measure_c1(torch, P, W, dev, steps: int) -> dict:
+    """The small Fourier configuration (d = 2, N = 64, q = 5, 4096 points):
+    launch-latency bound, so it is timed eagerly and as a captured HIP graph
+    replayed steps times."""
+    w = W.C1()
+    plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+    y, x, g = (torch.from_numpy(a).to(dev) for a in (w.y, w.x, w.g))
+    out = {"workload": "C1: Fourier phase on uniform grids, d=2, N=64, q=5 (r=25), 4096 points, 1 RHS",
+           "unit": "us per apply"}
+    for prec in ("fp32", "fp64"):
+        ws = plan.workspace(w.y.shape[0], w.nrhs, prec, device=dev)
+        f = torch.empty((w.nrhs, w.x.shape[0]), dtype=torch.complex128, device=dev)
+
+        def run():
+            plan.apply(y, g, x, prec, out=f, workspace=ws)
+
+        eager = time_steps(run, torch, steps, 5)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            run()
+        replay = time_steps(graph.replay, torch, steps, 5)
+        out[prec] = {"eager_us": round(eager * 1e3, 1), "graph_us": round(replay * 1e3, 1)}
+        print(f"[bench] C1 {prec}: eager {eager * 1e3:.1f} us, graph {replay * 1e3:.1f} us per apply",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def measure_sparse(torch, P, W, dev, steps: int) -> dict:
     """Sparse sets in the C2 geometry (N = 1024, q = 5): 4096 sources on a
     curve with all 1,048,576 grid targets, and 4096 targets on the curve with
@@ -298,6 +331,7 @@ def main() -> int:
     ap.add_argument("--no-c4", action="store_true", help="skip the 64-right-hand-side Fourier measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D generalized-Radon measurements")
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse source / target measurements")
+    ap.add_argument("--no-c1", action="store_true", help="skip the small (launch-bound) Fourier measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one plain device copy of 1 GiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -386,6 +420,7 @@ def main() -> int:
     c4 = None if args.no_c4 else measure_c4(torch, P, W, dev)
     r3d = None if args.no_3d else measure_3d(torch, P, W, dev, 5)
     sparse = None if args.no_sparse else measure_sparse(torch, P, W, dev, 10)
+    c1 = None if args.no_c1 else measure_c1(torch, P, W, dev, 200)
 
     head = "fp32"
     tim = res[head]["timing"]
@@ -435,6 +470,7 @@ def main() -> int:
         "c4_many_rhs": c4,
         "genradon_3d": r3d,
         "sparse_sets": sparse,
+        "c1_small": c1,
     }
     print(json.dumps(out), flush=True)
     return 0
