@@ -12,3 +12,10 @@ from .bfly import (BFLY_FP32, BFLY_FP64, Batch, BatchItem, BflyError, Plan, appl
                    bfly_apply_batched_autograd, bfly_batch_workspace_size, bfly_last_error, bfly_plan,
                    bfly_plan_destroy, bfly_plan_info, bfly_status_string, bfly_timing_enable, bfly_timing_read,
                    bfly_workspace_size, lib)
+
+
+def __getattr__(name):
+    if name == "BflyApply":
+        from . import bfly
+        return bfly.BflyApply
+    raise AttributeError(f"module {__name__!r} has no attribute {name!r}")

@@ -356,6 +356,18 @@ def _make_batch_autograd():
     return BflyBatchApply
 
 
+def __getattr__(name):
+    """BflyApply: the torch.autograd.Function of a forward apply (backward:
+    the adjoint apply), built on first access so that importing this module
+    does not import torch."""
+    if name == "BflyApply":
+        global _BflyApply
+        if _BflyApply is None:
+            _BflyApply = _make_autograd()
+        return _BflyApply
+    raise AttributeError(f"module {__name__!r} has no attribute {name!r}")
+
+
 def bfly_apply_autograd(g, plan: Plan, y, x, prec="fp64"):
     """Differentiable forward apply (see BflyApply)."""
     global _BflyApply

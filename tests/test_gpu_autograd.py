@@ -54,6 +54,19 @@ def test_autograd_backward_is_adjoint_butterfly(orc):
     assert e < 1e-12
 
 
+def test_bflyapply_function_name():
+    """The autograd Function is reachable as paper_1305_4650_amd.BflyApply and
+    gives the same gradient as bfly_apply_autograd."""
+    w = W.hypradon2(16, q=4, nrhs=1)
+    torch, P, plan, y, x, dev = _setup(w)
+    print("[case] BflyApply.apply", flush=True)
+    g1 = torch.from_numpy(w.g).to(dev).requires_grad_(True)
+    g2 = torch.from_numpy(w.g).to(dev).requires_grad_(True)
+    P.BflyApply.apply(g1, plan, y, x, "fp64").abs().pow(2).sum().backward()
+    P.bfly_apply_autograd(g2, plan, y, x, "fp64").abs().pow(2).sum().backward()
+    assert torch.equal(g1.grad, g2.grad)
+
+
 def test_gradient_matches_finite_differences():
     w = W.hypradon2(32, q=4, nrhs=1)
     torch, P, plan, y, x, dev = _setup(w)
