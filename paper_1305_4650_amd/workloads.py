@@ -91,7 +91,8 @@ class Workload:
 def fourier_grid(N: int, d: int = 2, q: int = 5, nrhs: int = 1, config_id: int = 1,
                  name: str | None = None) -> Workload:
     """Fourier kernel on uniform grids: y = j/N in [0,1)^d, x = k in [0,N)^d
-    (the C1 / C4 geometry; the direct sum is then an unnormalised inverse DFT)."""
+    (the uniform-grid Fourier geometry; the direct sum is then an
+    unnormalised inverse DFT)."""
     y = grid_points(N, np.zeros(d), np.ones(d))
     x = grid_points(N, np.zeros(d), np.full(d, float(N)))
     g = random_rhs(rng(config_id, 1), nrhs, N ** d)
