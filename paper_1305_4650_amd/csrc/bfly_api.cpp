@@ -169,6 +169,17 @@ int apply_common(bfly_plan_t plan, bool adjoint, int64_t n_in, const double* pin
 
 // ---- batched applies ----
 
+// An instance of at least this many leaves fills the GPU by itself (its
+// narrowest launch has thousands of workgroups): a batched apply runs it as a
+// single apply, in order on the stream, and batches only the smaller ones
+// level-synchronously.  (MI355X, 48 hyperbolic-Radon instances with N from
+// 128 to 1024 and 8 right-hand sides: level-synchronous launches over all of
+// them were 2-4% slower than back-to-back single applies, the small
+// instances' weights no longer staying in cache from one launch to the next.)
+constexpr uint64_t kSoloLeaves = (uint64_t)1 << 14;
+
+bool solo(const bfly_batch_item& it) { return ((uint64_t)1 << (it.plan->d * it.plan->L)) >= kSoloLeaves; }
+
 struct BLayout {
   std::vector<size_t> w;     // weights of each instance
   std::vector<uint32_t> leafbase;
@@ -212,6 +223,14 @@ int batch_layout(int n, const bfly_batch_item* items, int prec, BLayout* out) {
   while (bits < 32 && ((uint64_t)1 << bits) < L.leaves) ++bits;
   hipError_t e = bfly::sort_storage_bytes(L.n_total, bits, &L.tmp_bytes);
   if (e != hipSuccess) return fail(BFLY_EDEVICE, "sort storage query failed: %s", hipGetErrorString(e));
+  // instances run as single applies share the sort scratch
+  for (int k = 0; k < n; ++k) {
+    if (!solo(items[k])) continue;
+    size_t b = 0;
+    e = bfly::sort_storage_bytes(items[k].n_in, items[k].plan->d * items[k].plan->L, &b);
+    if (e != hipSuccess) return fail(BFLY_EDEVICE, "sort storage query failed: %s", hipGetErrorString(e));
+    L.tmp_bytes = std::max(L.tmp_bytes, b);
+  }
   const size_t nt = (size_t)L.n_total;
   L.keys = off;
   off += up(4 * nt);
@@ -252,16 +271,33 @@ int apply_batched(int n, const bfly_batch_item* items, int prec, void* ws, size_
   w.sort_tmp = base + L.tmp;
   w.sort_tmp_bytes = L.tmp_bytes;
   std::vector<bfly::Geo> geo(n);
-  std::vector<bfly::BinInst> bins(n);
-  std::vector<bfly::BatchInst> inst(n);
-  for (int k = 0; k < n; ++k) {
+  std::vector<bfly::BinInst> bins;
+  std::vector<bfly::BatchInst> inst;
+  int64_t n_small = 0;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < n && e == hipSuccess; ++k) {
     const bfly_batch_item& it = items[k];
     geo[k] = make_geo(*it.plan, it.adjoint != 0);
-    bins[k].pts = it.pts_in;
-    bins[k].n = it.n_in;
-    bins[k].G = &geo[k];
-    bins[k].leafbase = L.leafbase[k];
-    bfly::BatchInst& b = inst[k];
+    if (solo(it)) {
+      // a single apply on the shared buffers (in stream order, before the
+      // batched instances reuse them)
+      bfly::Work ws1 = w;
+      ws1.W = base + L.w[k];
+      ws1.idx = nullptr;
+      ws1.empty = w.offs + ((int64_t)1 << (it.plan->d * it.plan->L)) + 1;
+      ws1.tocc = nullptr;
+      e = bfly::run_apply(geo[k], prec, it.n_in, it.pts_in, static_cast<const double*>(it.in), it.ld_in, it.n_out,
+                          it.pts_out, static_cast<double*>(it.out), it.ld_out, it.nrhs, ws1, st);
+      continue;
+    }
+    bins.emplace_back();
+    inst.emplace_back();
+    n_small += it.n_in;
+    bins.back().pts = it.pts_in;
+    bins.back().n = it.n_in;
+    bins.back().G = &geo[k];
+    bins.back().leafbase = L.leafbase[k];
+    bfly::BatchInst& b = inst.back();
     b.G = geo[k];
     b.W = base + L.w[k];
     b.nrhs = it.nrhs;
@@ -274,15 +310,18 @@ int apply_batched(int n, const bfly_batch_item* items, int prec, void* ws, size_
     b.vals_out = static_cast<double*>(it.out);
     b.ld_out = it.ld_out;
   }
-  hipError_t e = bfly::bin_batch(bins.data(), n, L.n_total, L.leaves, w, st);
+  if (e != hipSuccess) return fail(BFLY_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  if (inst.empty()) return ok();
+  const int nb = (int)inst.size();
+  e = bfly::bin_batch(bins.data(), nb, n_small, L.leaves, w, st);
   if (e != hipSuccess) return fail(BFLY_EDEVICE, "binning launch failed: %s", hipGetErrorString(e));
   // groups of instances sharing d, q, phase and direction, in order of first appearance
-  std::vector<int> done(n, 0);
+  std::vector<int> done(nb, 0);
   int desc_next = 0;
-  for (int k = 0; k < n && e == hipSuccess; ++k) {
+  for (int k = 0; k < nb && e == hipSuccess; ++k) {
     if (done[k]) continue;
     std::vector<bfly::BatchInst> grp;
-    for (int j = k; j < n; ++j) {
+    for (int j = k; j < nb; ++j) {
       const bfly::Geo& a = inst[k].G;
       const bfly::Geo& b = inst[j].G;
       if (!done[j] && a.d == b.d && a.q == b.q && a.phase == b.phase && a.adj == b.adj) {
