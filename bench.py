@@ -296,6 +296,38 @@ def measure_sparse(torch, P, W, dev, steps: int) -> dict:
     return out
 
 
+def measure_adjoint(torch, P, w, plan, dev, steps: int, cores) -> dict:
+    """The adjoint apply g = B' f of the C2 plan (targets in, sources out,
+    phase negated, switch at L - L/2), with f = the C2 input values placed on
+    the 1,048,576 targets.  Timed per precision; with the oracle enabled, its
+    FP64 adjoint butterfly gives the relative errors."""
+    x = torch.from_numpy(w.x).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    fin = torch.from_numpy(w.g).to(dev)  # (nrhs, n_tgt): n_tgt = n_src in C2
+    out = {"workload": "C2 adjoint: f on the 1,048,576 grid targets -> g at the 1,048,576 jittered sources, "
+                       "N=1024, q=5, 1 right-hand side", "unit": "Mpoints/s"}
+    npts = w.N ** w.d * w.nrhs
+    got = {}
+    for prec in ("fp32", "fp64"):
+        ws = plan.workspace(w.x.shape[0], w.nrhs, prec, device=dev)
+        g = torch.empty((w.nrhs, w.y.shape[0]), dtype=torch.complex128, device=dev)
+        ms = time_steps(lambda: plan.apply_adjoint(x, fin, y, prec, out=g, workspace=ws), torch, steps, 2)
+        got[prec] = g.cpu().numpy()
+        out[prec] = {"ms": round(ms, 4), "value": round(npts / ms / 1e3, 3)}
+        print(f"[bench] adjoint {prec}: {ms:.3f} ms/apply  {npts / ms / 1e3:.1f} Mpoints/s", file=sys.stderr,
+              flush=True)
+        del ws
+    if cores:
+        import oracle
+        ref = oracle.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, w.x, w.g, w.y, adjoint=True,
+                               nthreads=cores)
+        for prec in got:
+            out[prec]["rel_err_vs_oracle"] = rel(got[prec], ref)
+        print(f"[bench] adjoint rel err vs oracle: fp64 {out['fp64']['rel_err_vs_oracle']:.2e} "
+              f"fp32 {out['fp32']['rel_err_vs_oracle']:.2e}", file=sys.stderr, flush=True)
+    return out
+
+
 def measure_3d(torch, P, W, dev, steps: int) -> dict:
     """The 3-D generalized-Radon configurations: the workload form (N = 64,
     q = 4, r = 64) and the phase as printed (N = 64, q = 5, r = 125), one
@@ -332,6 +364,7 @@ def main() -> int:
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D generalized-Radon measurements")
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse source / target measurements")
     ap.add_argument("--no-c1", action="store_true", help="skip the small (launch-bound) Fourier measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the C2 adjoint measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one plain device copy of 1 GiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -416,6 +449,8 @@ def main() -> int:
         print(f"[bench] oracle {t_cpu:.1f}s on {cores} threads; rel err fp64 "
               f"{res['fp64']['rel_err']:.2e} fp32 {res['fp32']['rel_err']:.2e}", file=sys.stderr, flush=True)
 
+    adj = None if args.no_adjoint else measure_adjoint(
+        torch, P, w, plan, dev, 10, None if args.no_cpu_baseline else (args.cpu_threads or len(os.sched_getaffinity(0))))
     c5 = None if args.no_c5 else measure_c5(torch, P, W, dev, max(3, args.steps // 4), 1)
     c4 = None if args.no_c4 else measure_c4(torch, P, W, dev)
     r3d = None if args.no_3d else measure_3d(torch, P, W, dev, 5)
@@ -466,6 +501,7 @@ def main() -> int:
         "roofline": roofline,
         "apply_roofline_fp32": apply_roofline,
         "cpu_baseline": cpu,
+        "adjoint": adj,
         "c5_batched": c5,
         "c4_many_rhs": c4,
         "genradon_3d": r3d,
