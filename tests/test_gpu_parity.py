@@ -121,10 +121,20 @@ def test_fp32_forward_parity(torch_dev, orc, name):
     assert e < FP32_TOL
 
 
-def test_fp32_adjoint_parity(torch_dev, orc):
-    w = W.hypradon2(64, q=5)
-    print("[case] fp32 adjoint hypradon2_N64_q5", flush=True)
-    vals = W.random_rhs(W.rng(w.config_id, 2), 1, w.x.shape[0])
+FP32_ADJ = {
+    "hypradon2_N64_q5": lambda: W.hypradon2(64, q=5),
+    "C1_fourier2d_N64_q5": lambda: W.C1(),
+    "fourier2d_N32_q6_9rhs": lambda: W.fourier_grid(32, d=2, q=6, nrhs=9),
+    "genradon3_N8_q4": lambda: W.genradon3(8, q=4),
+    "genradon3pi_N8_q5": lambda: W.genradon3pi(8, q=5),
+}
+
+
+@pytest.mark.parametrize("name", list(FP32_ADJ))
+def test_fp32_adjoint_parity(torch_dev, orc, name):
+    w = FP32_ADJ[name]()
+    print(f"[case] fp32 adjoint {name}", flush=True)
+    vals = W.random_rhs(W.rng(w.config_id, 2), w.nrhs, w.x.shape[0])
     e = rel(gpu_run(torch_dev, w, "fp32", adjoint=True, vals=vals), oracle_run(orc, w, adjoint=True, vals=vals))
     print(f"  rel err {e:.3e}", flush=True)
     assert e < FP32_TOL
@@ -222,6 +232,21 @@ def test_C2_full_fp32_parity(torch_dev, c2_oracle):
     e = rel(gpu_run(torch_dev, w, "fp32"), ref)
     print(f"  rel err {e:.3e}", flush=True)
     assert e < FP32_TOL
+
+
+def test_C2_full_adjoint_parity(torch_dev, orc):
+    """The adjoint apply at full C2 size (seeded values on the 1,048,576
+    targets, output at the 1,048,576 sources), both modes, against the
+    oracle's adjoint butterfly."""
+    w = W.C2()
+    vals = W.random_rhs(W.rng(w.config_id, 3), 1, w.x.shape[0])
+    print("[case] oracle C2 adjoint (full size)", flush=True)
+    ref = oracle_run(orc, w, adjoint=True, vals=vals)
+    for prec, tol in (("fp64", FP64_TOL), ("fp32", FP32_TOL)):
+        print(f"[case] {prec} adjoint C2 full", flush=True)
+        e = rel(gpu_run(torch_dev, w, prec, adjoint=True, vals=vals), ref)
+        print(f"  rel err {e:.3e}", flush=True)
+        assert e < tol
 
 
 def test_C2_gap_to_direct_sum(torch_dev, orc, c2_oracle):
