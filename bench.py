@@ -27,7 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(ROOT, "paper_1305_4650_amd", "csrc")
 PEAK_VALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, non-packed VALU issue rate
 
-# Flops charged per evaluation of tau (sqrt, sin and cos as below), see the design doc.
+# Flops charged per evaluation of tau (the operations of its definition; sqrt and the
+# sine/cosine pair counted as below).
 SINCOS_FLOPS = 28  # sin + cos pair of a reduced argument (two Horner polynomials)
 TAU_FLOPS = {"fourier": lambda d: 2 * d - 1, "hypradon2": lambda d: 6, "genradon3": lambda d: 80,
              "genradon3pi": lambda d: 78,
@@ -378,7 +379,7 @@ def main() -> int:
         print(json.dumps({"copy_bytes": a.numel() * 4}))
         return 0
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (got --gpus {args.gpus}); "
               "the apply does not shard across GPUs.", file=sys.stderr)
         return 2
 
