@@ -27,7 +27,7 @@ constexpr int kBlock = 256;
 // Passes go from the lowest digit (at most kMaxDigit bits) up; each pass is a
 // stable counting sort by its digit, so the passes together give the stable
 // sort by the whole key.  A pass is three launches:
-//   k_digit_hist     digit counts of every tile of kTile keys, stored
+//   k_digit_hist     digit counts of every tile of 256 KPT keys, stored
 //                    digit-major: cnt[digit * ntile + tile]
 //   k_digit_scan     exclusive prefix of each digit's row over the tiles (in
 //                    place) and the row total tot[digit]
@@ -39,13 +39,17 @@ constexpr int kBlock = 256;
 // permutation is the same on every run.
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortKeys = 16;  // keys per thread
-constexpr int kTile = kSortThreads * kSortKeys;
 constexpr int kMaxDigit = 11;
+
+// Keys per thread (KPT) of the histogram and scatter kernels, from n alone
+// (so workspace queries and applies agree): 16 for large sorts (fewer tiles,
+// shorter count rows); small sorts take fewer, since a tile ranks its keys
+// 64 at a time in a serial loop and more, shorter tiles run side by side.
+inline int sort_kpt(int64_t n) { return n > (1 << 18) ? 16 : n > (1 << 14) ? 8 : 2; }
 
 struct SortPlan {
   int passes = 0, width[3] = {0, 0, 0}, shift[3] = {0, 0, 0}, maxw = 0;
-  int ntile = 0;
+  int ntile = 0, kpt = 0;
 };
 
 SortPlan sort_plan(int64_t n, int bits) {
@@ -59,7 +63,9 @@ SortPlan sort_plan(int64_t n, int bits) {
     sh += s.width[p];
     s.maxw = std::max(s.maxw, s.width[p]);
   }
-  s.ntile = (int)((n + kTile - 1) / kTile);
+  s.kpt = sort_kpt(n);
+  const int64_t tile = (int64_t)kSortThreads * s.kpt;
+  s.ntile = (int)((n + tile - 1) / tile);
   return s;
 }
 
@@ -75,22 +81,23 @@ size_t sort_bytes(const SortPlan& s, int64_t n) {
   return b;
 }
 
+template <int KPT>
 __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                              int nb, int ntile, int32_t* __restrict__ cnt) {
   __shared__ int32_t h[1 << kMaxDigit];
   const int B = 1 << nb;
   for (int i = threadIdx.x; i < B; i += kSortThreads) h[i] = 0;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t e0 = (int64_t)blockIdx.x * kTile + (int64_t)w * 64 * kSortKeys + lane;
-  uint32_t k[kSortKeys];
+  const int64_t e0 = (int64_t)blockIdx.x * (kSortThreads * KPT) + (int64_t)w * 64 * KPT + lane;
+  uint32_t k[KPT];
 #pragma unroll
-  for (int c = 0; c < kSortKeys; ++c) {
+  for (int c = 0; c < KPT; ++c) {
     const int64_t e = e0 + c * 64;
     k[c] = e < n ? keys[e] : 0u;
   }
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < kSortKeys; ++c)
+  for (int c = 0; c < KPT; ++c)
     if (e0 + c * 64 < n) atomicAdd(&h[(k[c] >> shift) & (uint32_t)(B - 1)], 1);
   __syncthreads();
   for (int i = threadIdx.x; i < B; i += kSortThreads) cnt[(int64_t)i * ntile + blockIdx.x] = h[i];
@@ -132,6 +139,7 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_scan(int nb, int ntile, 
 }
 
 // vals == nullptr: the payload of key e is e
+template <int KPT>
 __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(const uint32_t* __restrict__ keys,
                                                                 const int32_t* __restrict__ vals, int64_t n, int shift,
                                                                 int nb, int ntile, const int32_t* __restrict__ cnt,
@@ -143,21 +151,21 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(const uint32_t* 
   const int B = 1 << nb;
   const uint32_t mask = (uint32_t)(B - 1);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t e0 = (int64_t)blockIdx.x * kTile + (int64_t)w * 64 * kSortKeys + lane;
-  uint32_t k[kSortKeys];
-  int32_t v[kSortKeys];
+  const int64_t e0 = (int64_t)blockIdx.x * (kSortThreads * KPT) + (int64_t)w * 64 * KPT + lane;
+  uint32_t k[KPT];
+  int32_t v[KPT];
 #pragma unroll
-  for (int c = 0; c < kSortKeys; ++c) {
+  for (int c = 0; c < KPT; ++c) {
     const int64_t e = e0 + c * 64;
     k[c] = e < n ? keys[e] : 0u;
     v[c] = e < n ? (vals ? vals[e] : (int32_t)e) : 0;
   }
-  // every wave counts its own 64 * kSortKeys keys in its own row of h
+  // every wave counts its own 64 KPT keys in its own row of h
   for (int i = lane; i < B; i += 64) h[w][i] = 0;
   const uint64_t lower = (1ull << lane) - 1ull;
-  int32_t r[kSortKeys];
+  int32_t r[KPT];
 #pragma unroll
-  for (int c = 0; c < kSortKeys; ++c) {
+  for (int c = 0; c < KPT; ++c) {
     const bool ok = e0 + c * 64 < n;
     const uint32_t d = (k[c] >> shift) & mask;
     uint64_t peers = __ballot(ok);
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(const uint32_t* 
   }
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < kSortKeys; ++c) {
+  for (int c = 0; c < KPT; ++c) {
     if (e0 + c * 64 < n) {
       const int64_t dst = (int64_t)h[w][(k[c] >> shift) & mask] + r[c];
       if (dst >= 0 && dst < n) {
@@ -216,6 +224,15 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(const uint32_t* 
       }
     }
   }
+}
+
+template <int KPT>
+void sort_pass(const SortPlan& s, int pass, const uint32_t* kin, const int32_t* vin, int64_t n, int32_t* cnt,
+               int32_t* tot, uint32_t* ko, int32_t* vo, hipStream_t st) {
+  const int nb = s.width[pass];
+  k_digit_hist<KPT><<<s.ntile, kSortThreads, 0, st>>>(kin, n, s.shift[pass], nb, s.ntile, cnt);
+  k_digit_scan<<<((1 << nb) + kSortWaves - 1) / kSortWaves, kSortThreads, 0, st>>>(nb, s.ntile, cnt, tot);
+  k_digit_scatter<KPT><<<s.ntile, kSortThreads, 0, st>>>(kin, vin, n, s.shift[pass], nb, s.ntile, cnt, tot, ko, vo);
 }
 
 // Stable sort of (keys, vals) by the low `bits` bits of the keys into
@@ -240,10 +257,12 @@ hipError_t radix_sort(const uint32_t* keys, const int32_t* vals, int64_t n, int 
     const bool to_out = ((s.passes - 1 - pass) & 1) == 0;
     uint32_t* ko = to_out ? keys_out : k_alt;
     int32_t* vo = to_out ? vals_out : v_alt;
-    const int nb = s.width[pass];
-    k_digit_hist<<<s.ntile, kSortThreads, 0, st>>>(kin, n, s.shift[pass], nb, s.ntile, cnt);
-    k_digit_scan<<<((1 << nb) + kSortWaves - 1) / kSortWaves, kSortThreads, 0, st>>>(nb, s.ntile, cnt, tot);
-    k_digit_scatter<<<s.ntile, kSortThreads, 0, st>>>(kin, vin, n, s.shift[pass], nb, s.ntile, cnt, tot, ko, vo);
+    if (s.kpt == 16)
+      sort_pass<16>(s, pass, kin, vin, n, cnt, tot, ko, vo, st);
+    else if (s.kpt == 8)
+      sort_pass<8>(s, pass, kin, vin, n, cnt, tot, ko, vo, st);
+    else
+      sort_pass<2>(s, pass, kin, vin, n, cnt, tot, ko, vo, st);
     kin = ko;
     vin = vo;
   }
