@@ -183,6 +183,28 @@ def test_empty_and_uneven_inputs(torch_dev, orc):
     assert rel(fo, ref) < 1e-12 * 1e5
 
 
+@pytest.mark.parametrize("N, extra", [(128, 1), (128, 2047), (512, 1)])
+def test_sort_tile_boundaries(torch_dev, orc, N, extra):
+    """Source counts just past the leaf-key sort's tile-size switches (2^14
+    and 2^18 keys: 512-, 2048- and 4096-key tiles) with a ragged last tile:
+    the grid sources plus `extra` more drawn uniformly in the source box, so
+    that some leaves hold two or more points."""
+    import paper_1305_4650_amd as P
+    torch = torch_dev
+    w = W.hypradon2(N, q=3)
+    gen = W.rng(w.config_id, 7)
+    ys = np.concatenate([w.y, w.src_lo + gen.random((extra, 2)) * (w.src_hi - w.src_lo)])
+    gs = W.random_rhs(gen, 1, ys.shape[0])
+    print(f"[case] sort tiles N={N} n_src={ys.shape[0]}", flush=True)
+    plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+    f = plan.apply(torch.from_numpy(ys).cuda(), torch.from_numpy(gs).cuda(), torch.from_numpy(w.x).cuda())
+    torch.cuda.synchronize()
+    ref = orc.butterfly(w.phase, w.N, w.q, w.src_box, w.tgt_box, ys, gs, w.x)
+    e = rel(f.cpu().numpy(), ref)
+    print(f"  rel err {e:.3e}", flush=True)
+    assert e < FP64_TOL
+
+
 def test_repeatable_bitwise(torch_dev):
     """Same inputs, same bits: no atomics in any accumulation."""
     w = W.hypradon2(64, q=5)
