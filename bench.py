@@ -329,6 +329,27 @@ def measure_adjoint(torch, P, w, plan, dev, steps: int, cores) -> dict:
     return out
 
 
+def measure_rhs(torch, P, W, dev, steps: int) -> dict:
+    """The C2 geometry with 8 right-hand sides in one apply (chunks of 2
+    share their phase factors), timed with events; reported per right-hand
+    side."""
+    w = W.hypradon2(1024, q=5, nrhs=8)
+    plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+    y, x, g = (torch.from_numpy(a).to(dev) for a in (w.y, w.x, w.g))
+    pts = w.N ** w.d * w.nrhs
+    out = {"workload": "C2 geometry (2-D hyperbolic Radon, N=1024, q=5), 8 right-hand sides in one apply",
+           "unit": "Mpoints/s"}
+    for prec in ("fp32", "fp64"):
+        ws = plan.workspace(w.y.shape[0], w.nrhs, prec, device=dev)
+        f = torch.empty((w.nrhs, w.x.shape[0]), dtype=torch.complex128, device=dev)
+        ms = time_steps(lambda: plan.apply(y, g, x, prec, out=f, workspace=ws), torch, steps, 2)
+        out[prec] = {"ms": round(ms, 3), "ms_per_rhs": round(ms / w.nrhs, 4), "value": round(pts / ms / 1e3, 3)}
+        print(f"[bench] C2 8 rhs {prec}: {ms:.2f} ms ({ms / w.nrhs:.3f} ms per rhs) -> {pts / ms / 1e3:.1f} Mpoints/s",
+              file=sys.stderr, flush=True)
+        del ws
+    return out
+
+
 def measure_3d(torch, P, W, dev, steps: int) -> dict:
     """The 3-D generalized-Radon configurations: the workload form (N = 64,
     q = 4, r = 64) and the phase as printed (N = 64, q = 5, r = 125), one
@@ -366,6 +387,7 @@ def main() -> int:
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse source / target measurements")
     ap.add_argument("--no-c1", action="store_true", help="skip the small (launch-bound) Fourier measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the C2 adjoint measurement")
+    ap.add_argument("--no-rhs", action="store_true", help="skip the C2 8-right-hand-side measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one plain device copy of 1 GiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -452,6 +474,7 @@ def main() -> int:
 
     adj = None if args.no_adjoint else measure_adjoint(
         torch, P, w, plan, dev, 10, None if args.no_cpu_baseline else (args.cpu_threads or len(os.sched_getaffinity(0))))
+    rhs8 = None if args.no_rhs else measure_rhs(torch, P, W, dev, 10)
     c5 = None if args.no_c5 else measure_c5(torch, P, W, dev, max(3, args.steps // 4), 1)
     c4 = None if args.no_c4 else measure_c4(torch, P, W, dev)
     r3d = None if args.no_3d else measure_3d(torch, P, W, dev, 5)
@@ -503,6 +526,7 @@ def main() -> int:
         "apply_roofline_fp32": apply_roofline,
         "cpu_baseline": cpu,
         "adjoint": adj,
+        "c2_8rhs": rhs8,
         "c5_batched": c5,
         "c4_many_rhs": c4,
         "genradon_3d": r3d,
