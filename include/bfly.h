@@ -81,10 +81,16 @@ enum {
 };
 
 /* precision modes (internal arithmetic; I/O is always complex128)
- *  FP64   everything in FP64 (the paper computes in double precision, Sec. 3).
- *  FP32   phase tau and its reduction modulo 1 in FP64, then FP32
- *         sine/cosine, FP32 weights and FP32 contractions. */
-enum { BFLY_FP64 = 0, BFLY_FP32 = 1 };
+ *  FP64     everything in FP64 (the paper computes in double precision, Sec. 3).
+ *  FP32     phase tau and its reduction modulo 1 in FP64, then FP32
+ *           sine/cosine, FP32 weights and FP32 contractions.
+ *  SPLIT32  hi/lo pairs of FP32 values with error-free accumulation: NOT
+ *           built.  Every entry point that takes a precision returns
+ *           BFLY_EUNSUPPORTED for it.  On gfx950 the FP64 vector unit issues
+ *           at the non-packed FP32 rate, and a double-float multiply-add
+ *           takes 18 FP32 instructions (measured 7.3x slower than an FP64
+ *           multiply-add), so the FP64 mode gives near-FP64 results faster. */
+enum { BFLY_FP64 = 0, BFLY_FP32 = 1, BFLY_SPLIT32 = 2 };
 
 /* Create a plan.
  *  d        1, 2 or 3
@@ -110,9 +116,9 @@ int bfly_plan_info(bfly_plan_t plan, int64_t* out5);
 
 /* Device workspace, in bytes, needed by one apply (forward or adjoint) with
  * n_in input points, nrhs right-hand sides and precision prec.  n_in is
- * n_src for bfly_apply and n_tgt for bfly_apply_adjoint.  May call into
- * HIP to size library sort storage; never allocates.
- * Returns BFLY_OK, BFLY_EINVAL or BFLY_EDEVICE. */
+ * n_src for bfly_apply and n_tgt for bfly_apply_adjoint.  A host
+ * computation only: no HIP call, no allocation.
+ * Returns BFLY_OK or BFLY_EINVAL. */
 int bfly_workspace_size(bfly_plan_t plan, int64_t n_in, int nrhs, int prec, size_t* bytes);
 
 /* Forward apply f = B g  (B ~= K restricted to the points).

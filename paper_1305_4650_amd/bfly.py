@@ -18,10 +18,11 @@ LIB_PATH = os.environ.get("BFLY_LIBRARY") or os.path.join(HERE, "libbfly.so")
 
 BFLY_OK, BFLY_EINVAL, BFLY_EUNSUPPORTED, BFLY_ENOMEM, BFLY_EDEVICE, BFLY_EWORKSPACE = range(6)
 BFLY_PHASE_FOURIER, BFLY_PHASE_HYPRADON2, BFLY_PHASE_GENRADON3, BFLY_PHASE_SEPARABLE_TEST = range(4)
-BFLY_FP64, BFLY_FP32 = 0, 1
+BFLY_FP64, BFLY_FP32, BFLY_SPLIT32 = 0, 1, 2
 
 PHASES = {"fourier": 0, "hypradon2": 1, "genradon3": 2, "separable": 3, "genradon3pi": 4}
-PRECISIONS = {"fp64": BFLY_FP64, "fp32": BFLY_FP32}
+# "split32" is a valid mode that the library does not build (BFLY_EUNSUPPORTED)
+PRECISIONS = {"fp64": BFLY_FP64, "fp32": BFLY_FP32, "split32": BFLY_SPLIT32}
 
 EXPORTS = ("bfly_plan", "bfly_plan_destroy", "bfly_plan_info", "bfly_workspace_size", "bfly_apply",
            "bfly_apply_adjoint", "bfly_batch_workspace_size", "bfly_apply_batched", "bfly_timing_enable",

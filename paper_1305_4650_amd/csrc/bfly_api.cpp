@@ -113,6 +113,15 @@ int layout(const bfly_plan_s& p, int64_t n_in, int nrhs, int prec, Layout* out) 
   return BFLY_OK;
 }
 
+// FP64 and FP32 are built; SPLIT32 is a valid mode that this build does not
+// provide (see include/bfly.h)
+int check_prec(int prec) {
+  if (prec == BFLY_SPLIT32)
+    return fail(BFLY_EUNSUPPORTED, "precision mode SPLIT32 is not built: FP64 runs at the FP32 rate on gfx950");
+  if (prec != BFLY_FP64 && prec != BFLY_FP32) return fail(BFLY_EINVAL, "unknown precision mode %d", prec);
+  return BFLY_OK;
+}
+
 int check_plan(const bfly_plan_s* p) {
   if (!p) return fail(BFLY_EINVAL, "plan is NULL");
   return BFLY_OK;
@@ -136,7 +145,7 @@ int apply_common(bfly_plan_t plan, bool adjoint, int64_t n_in, const double* pin
   if (n_in < 0 || n_in >= ((int64_t)1 << 31)) return fail(BFLY_EINVAL, "%s out of range", nin);
   if (n_out < 0 || n_out >= ((int64_t)1 << 31)) return fail(BFLY_EINVAL, "%s out of range", nout);
   if (nrhs < 1 || nrhs > 4096) return fail(BFLY_EINVAL, "nrhs must be in [1, 4096]");
-  if (prec != BFLY_FP64 && prec != BFLY_FP32) return fail(BFLY_EINVAL, "unknown precision mode %d", prec);
+  if (int rc = check_prec(prec)) return rc;
   if (ldin < n_in || ldin < 1) return fail(BFLY_EINVAL, "leading dimension of the input < number of inputs");
   if (ldout < n_out || ldout < 1) return fail(BFLY_EINVAL, "leading dimension of the output < number of outputs");
   if (n_in > 0 && (!pin || !vin)) return fail(BFLY_EINVAL, "input points or values are NULL");
@@ -182,10 +191,11 @@ bool solo(const bfly_batch_item& it) { return ((uint64_t)1 << (it.plan->d * it.p
 
 struct BLayout {
   std::vector<size_t> w;     // weights of each instance
-  std::vector<uint32_t> leafbase;
+  std::vector<uint32_t> leafbase;  // first key of each batched (not solo) instance
   size_t keys = 0, keys_sorted = 0, idx = 0, perm = 0, offs = 0, desc = 0, tmp = 0, total = 0, tmp_bytes = 0;
-  int64_t n_total = 0;
-  uint64_t leaves = 0;
+  int64_t n_small = 0;       // input points of the batched instances (the one sort)
+  uint64_t leaves = 0;       // leaves of the batched instances (its key space)
+  int bits = 0;              // key bits of that sort
 };
 
 int check_item(const bfly_batch_item& it, int k) {
@@ -205,25 +215,43 @@ int check_item(const bfly_batch_item& it, int k) {
 int batch_layout(int n, const bfly_batch_item* items, int prec, BLayout* out) {
   if (n < 1 || n > 4096) return fail(BFLY_EINVAL, "n_items must be in [1, 4096]");
   if (!items) return fail(BFLY_EINVAL, "items is NULL");
-  if (prec != BFLY_FP64 && prec != BFLY_FP32) return fail(BFLY_EINVAL, "unknown precision mode %d", prec);
+  if (int rc = check_prec(prec)) return rc;
   BLayout L;
   size_t off = 0;
+  uint64_t leaves_all = 0;
+  int64_t n_all = 0;
+  // the point and leaf buffers are shared in stream order: the instances run
+  // as single applies use them one after another (their own n and N^d), then
+  // the batched instances use them together (one key space)
+  int64_t n_max = 0;
+  uint64_t leaves_max = 0;
   for (int k = 0; k < n; ++k) {
     if (int rc = check_item(items[k], k)) return rc;
     const bfly_plan_s& p = *items[k].plan;
     L.w.push_back(off);
     off += up(bfly::weight_bytes(make_geo(p, items[k].adjoint != 0), items[k].nrhs, prec));
-    L.leafbase.push_back((uint32_t)L.leaves);
-    L.leaves += (uint64_t)1 << (p.d * p.L);
-    L.n_total += items[k].n_in;
-    if (L.leaves > ((uint64_t)1 << 31)) return fail(BFLY_EINVAL, "total leaves of the batch exceed 2^31");
-    if (L.n_total >= ((int64_t)1 << 31)) return fail(BFLY_EINVAL, "total input points of the batch reach 2^31");
+    const uint64_t P = (uint64_t)1 << (p.d * p.L);
+    leaves_all += P;
+    n_all += items[k].n_in;
+    if (leaves_all > ((uint64_t)1 << 31)) return fail(BFLY_EINVAL, "total leaves of the batch exceed 2^31");
+    if (n_all >= ((int64_t)1 << 31)) return fail(BFLY_EINVAL, "total input points of the batch reach 2^31");
+    if (solo(items[k])) {
+      L.leafbase.push_back(0);
+      n_max = std::max(n_max, items[k].n_in);
+      leaves_max = std::max(leaves_max, P);
+    } else {
+      L.leafbase.push_back((uint32_t)L.leaves);
+      L.leaves += P;
+      L.n_small += items[k].n_in;
+    }
   }
-  int bits = 0;
-  while (bits < 32 && ((uint64_t)1 << bits) < L.leaves) ++bits;
-  hipError_t e = bfly::sort_storage_bytes(L.n_total, bits, &L.tmp_bytes);
+  n_max = std::max(n_max, L.n_small);
+  leaves_max = std::max(leaves_max, L.leaves);
+  while (L.bits < 32 && ((uint64_t)1 << L.bits) < L.leaves) ++L.bits;
+  // sort scratch: the batched sort of n_small keys, and each single apply's
+  // own sort (the scratch size is not monotone in n: the tile size changes)
+  hipError_t e = bfly::sort_storage_bytes(L.n_small, L.bits, &L.tmp_bytes);
   if (e != hipSuccess) return fail(BFLY_EDEVICE, "sort storage query failed: %s", hipGetErrorString(e));
-  // instances run as single applies share the sort scratch
   for (int k = 0; k < n; ++k) {
     if (!solo(items[k])) continue;
     size_t b = 0;
@@ -231,7 +259,7 @@ int batch_layout(int n, const bfly_batch_item* items, int prec, BLayout* out) {
     if (e != hipSuccess) return fail(BFLY_EDEVICE, "sort storage query failed: %s", hipGetErrorString(e));
     L.tmp_bytes = std::max(L.tmp_bytes, b);
   }
-  const size_t nt = (size_t)L.n_total;
+  const size_t nt = (size_t)n_max;
   L.keys = off;
   off += up(4 * nt);
   L.keys_sorted = off;
@@ -241,7 +269,7 @@ int batch_layout(int n, const bfly_batch_item* items, int prec, BLayout* out) {
   L.perm = off;
   off += up(4 * nt);
   L.offs = off;
-  off += up(4 * (L.leaves + 2));  // offsets, then the empty-leaf flag
+  off += up(4 * (leaves_max + 2));  // offsets, then the empty-leaf flag
   L.desc = off;
   off += up(2 * (size_t)n * sizeof(bfly::ItemDesc));
   L.tmp = off;
@@ -313,6 +341,7 @@ int apply_batched(int n, const bfly_batch_item* items, int prec, void* ws, size_
   if (e != hipSuccess) return fail(BFLY_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   if (inst.empty()) return ok();
   const int nb = (int)inst.size();
+  if (n_small != L.n_small) return fail(BFLY_EINVAL, "internal: batched point count mismatch");
   e = bfly::bin_batch(bins.data(), nb, n_small, L.leaves, w, st);
   if (e != hipSuccess) return fail(BFLY_EDEVICE, "binning launch failed: %s", hipGetErrorString(e));
   // groups of instances sharing d, q, phase and direction, in order of first appearance
@@ -416,7 +445,7 @@ int bfly_workspace_size(bfly_plan_t plan, int64_t n_in, int nrhs, int prec, size
   if (!bytes) return fail(BFLY_EINVAL, "bytes is NULL");
   if (n_in < 0 || n_in >= ((int64_t)1 << 31)) return fail(BFLY_EINVAL, "n_in out of range");
   if (nrhs < 1 || nrhs > 4096) return fail(BFLY_EINVAL, "nrhs must be in [1, 4096]");
-  if (prec != BFLY_FP64 && prec != BFLY_FP32) return fail(BFLY_EINVAL, "unknown precision mode %d", prec);
+  if (int rc = check_prec(prec)) return rc;
   Layout L;
   if (int rc = layout(*plan, n_in, nrhs, prec, &L)) return rc;
   *bytes = L.total;

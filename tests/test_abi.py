@@ -111,6 +111,57 @@ def test_apply_rejects_invalid_arguments_on_host():
     assert L.bfly_workspace_size(p.handle, -3, 1, 0, ctypes.byref(out)) == B.BFLY_EINVAL
 
 
+def test_split32_is_rejected_as_unsupported():
+    """The hi/lo split-FP32 mode is a declared precision that the library does
+    not build: every entry point taking a precision returns
+    BFLY_EUNSUPPORTED for it, on the host, before any HIP call."""
+    p = P.Plan(2, 16, BOX2, TBOX2, "hypradon2", 4)
+    L = B.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.bfly_apply(p.handle, 256, fake, fake, 256, 256, fake, fake, 256, 1, B.BFLY_SPLIT32, fake, 1 << 30,
+                        None) == B.BFLY_EUNSUPPORTED
+    assert "SPLIT32" in P.bfly_last_error()
+    assert L.bfly_apply_adjoint(p.handle, 256, fake, fake, 256, 256, fake, fake, 256, 1, B.BFLY_SPLIT32, fake,
+                                1 << 30, None) == B.BFLY_EUNSUPPORTED
+    out = ctypes.c_size_t()
+    assert L.bfly_workspace_size(p.handle, 256, 1, B.BFLY_SPLIT32, ctypes.byref(out)) == B.BFLY_EUNSUPPORTED
+    it = B.BatchItem(p.handle, 0, 1, 256, 0x1000, 0x1000, 256, 256, 0x1000, 0x1000, 256)
+    arr = (B.BatchItem * 1)(it)
+    assert L.bfly_batch_workspace_size(1, arr, B.BFLY_SPLIT32, ctypes.byref(out)) == B.BFLY_EUNSUPPORTED
+    assert L.bfly_apply_batched(1, arr, B.BFLY_SPLIT32, fake, 1 << 40, None) == B.BFLY_EUNSUPPORTED
+    with pytest.raises(P.BflyError) as ei:
+        p.workspace_size(256, 1, "split32")
+    assert ei.value.code == B.BFLY_EUNSUPPORTED
+
+
+def test_batch_workspace_covers_mixed_batches():
+    """A batch of small instances (sorted together) and one large instance
+    (run as a single apply inside the call): the workspace covers both uses
+    of the shared buffers, also where the batched point count sits at the
+    sort's tile-size switches (2^14 and 2^18 keys), whose scratch is not
+    monotone in the number of keys."""
+    small = P.Plan(2, 64, BOX2, TBOX2, "hypradon2", 5)
+    big = P.Plan(2, 128, BOX2, TBOX2, "hypradon2", 5)
+    fake = 0x1000
+
+    def item(plan, n):
+        return B.BatchItem(plan.handle, 0, 1, n, fake, fake, n, n, fake, fake, n)
+
+    def size(items):
+        arr = (B.BatchItem * len(items))(*items)
+        return B.bfly_batch_workspace_size(arr, B.BFLY_FP64)
+
+    for n_small_each, count, n_big in ((4096, 64, 20000), (5461, 3, 30000), (4096, 4, 16383)):
+        only_small = size([item(small, n_small_each)] * count)
+        only_big = size([item(big, n_big)])
+        mixed = size([item(small, n_small_each)] * count + [item(big, n_big)])
+        # the mixed workspace holds both instance sets' weights and the larger
+        # of their point, leaf and sort buffers
+        weights_big = 128 * 128 * 25 * 16
+        assert mixed >= only_small + weights_big, (n_small_each, count, n_big)
+        assert mixed >= only_big, (n_small_each, count, n_big)
+
+
 def test_binding_has_no_cpu_fallback(monkeypatch, tmp_path):
     """Without the built library the binding raises instead of computing."""
     monkeypatch.setattr(B, "_lib", None)

@@ -231,3 +231,32 @@ def test_c5_gradient_matches_finite_differences():
         scale = np.abs(grad).max()
         print(f"  instance {k} N={w.N}: fd max err / max|grad| = {err / scale:.3e}", flush=True)
         assert err / scale < 1e-7, k
+
+
+@pytest.mark.parametrize("count, n_each, n_big", [(3, 5461, 30000), (64, 4096, 20000), (4, 4095, 70000)])
+def test_mixed_batch_at_sort_tile_switches(count, n_each, n_big):
+    """Small instances (N = 64: sorted together) with a batched point total
+    just below or at the sort's tile-size switches (2^14 = 16384 and 2^18 =
+    262144 keys), plus one large instance (N = 128 with more points than
+    leaves: run as a single apply inside the call, which uses the shared
+    sort scratch for its own sort).  Every output equals the instance's own
+    single apply bit for bit."""
+    gen = np.random.default_rng([count, n_each, n_big])
+    box = (np.array([1.0, 0.0]), np.array([2.0, 1.0]))
+    tbox = (np.zeros(2), np.ones(2))
+    small = P.Plan(2, 64, box, tbox, "hypradon2", 4)
+    big = P.Plan(2, 128, box, tbox, "hypradon2", 4)
+    print(f"[case] mixed batch {count} x {n_each} + {n_big} (batched points {count * n_each})", flush=True)
+    items = []
+    for k in range(count + 1):
+        plan, n = (big, n_big) if k == count else (small, n_each)
+        y = box[0] + gen.random((n, 2)) * (box[1] - box[0])
+        x = gen.random((257, 2))
+        g = W.random_rhs(gen, 1, n)
+        items.append((plan, False, _dev(y), _dev(g), _dev(x)))
+    outs = P.apply_batched(items, "fp64")
+    torch.cuda.synchronize()
+    for k, (plan, _, y, g, x) in enumerate(items):
+        single = plan.apply(y, g, x, "fp64")
+        torch.cuda.synchronize()
+        assert torch.equal(outs[k], single), f"instance {k}"
