@@ -138,6 +138,30 @@ int bfly_apply(bfly_plan_t plan,
                int64_t n_tgt, const double* x, void* f, int64_t ldf,
                int nrhs, int prec, void* ws, size_t ws_bytes, void* stream);
 
+/* Forward apply without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops and
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * bfly_apply; the workspace is a device array inside the library, one copy
+ * per GPU, of BFLY_NOALLOC_MAX_BYTES bytes, held from the library's load on
+ * that GPU to the end of the process.  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine); its first call on a
+ * device looks up that device's copy (hipGetSymbolAddress).
+ * Limits and sharing:
+ *  - an apply whose bfly_workspace_size(plan, n_src, nrhs, prec) exceeds
+ *    BFLY_NOALLOC_MAX_BYTES returns BFLY_EWORKSPACE before any HIP call
+ *    (e.g. 2-D, q = 5, one right-hand side: N = 256 fits in FP64 and FP32,
+ *    N = 1024 does not);
+ *  - every call on one GPU uses that GPU's one array: calls that overlap in
+ *    time on one GPU (several streams or host threads) race and give wrong
+ *    results; calls in one stream's order are safe.  Nothing in the array
+ *    needs to start at zero, so the previous call's contents do no harm.
+ * Returns BFLY_OK, BFLY_EINVAL, BFLY_EWORKSPACE or BFLY_EDEVICE. */
+#define BFLY_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int bfly_apply_noalloc(bfly_plan_t plan,
+                       int64_t n_src, const double* y, const void* g, int64_t ldg,
+                       int64_t n_tgt, const double* x, void* f, int64_t ldf,
+                       int nrhs, int prec, void* stream);
+
 /* Adjoint apply g_out = B' f_in, where B' is the butterfly for the adjoint
  * kernel K^H(y, x) = exp(-i Phi(x, y)): the same steps with the roles of
  * the two point sets swapped and the phase negated (Sec. 1: the low-rank

@@ -19,14 +19,15 @@ LIB_PATH = os.environ.get("BFLY_LIBRARY") or os.path.join(HERE, "libbfly.so")
 BFLY_OK, BFLY_EINVAL, BFLY_EUNSUPPORTED, BFLY_ENOMEM, BFLY_EDEVICE, BFLY_EWORKSPACE = range(6)
 BFLY_PHASE_FOURIER, BFLY_PHASE_HYPRADON2, BFLY_PHASE_GENRADON3, BFLY_PHASE_SEPARABLE_TEST = range(4)
 BFLY_FP64, BFLY_FP32, BFLY_SPLIT32 = 0, 1, 2
+BFLY_NOALLOC_MAX_BYTES = 64 << 20  # workspace held by the library for bfly_apply_noalloc
 
 PHASES = {"fourier": 0, "hypradon2": 1, "genradon3": 2, "separable": 3, "genradon3pi": 4}
 # "split32" is a valid mode that the library does not build (BFLY_EUNSUPPORTED)
 PRECISIONS = {"fp64": BFLY_FP64, "fp32": BFLY_FP32, "split32": BFLY_SPLIT32}
 
 EXPORTS = ("bfly_plan", "bfly_plan_destroy", "bfly_plan_info", "bfly_workspace_size", "bfly_apply",
-           "bfly_apply_adjoint", "bfly_batch_workspace_size", "bfly_apply_batched", "bfly_timing_enable",
-           "bfly_timing_read", "bfly_status_string", "bfly_last_error")
+           "bfly_apply_noalloc", "bfly_apply_adjoint", "bfly_batch_workspace_size", "bfly_apply_batched",
+           "bfly_timing_enable", "bfly_timing_read", "bfly_status_string", "bfly_last_error")
 STEP_NAMES = ("binning", "first", "second", "final")
 
 
@@ -70,6 +71,8 @@ def lib() -> ctypes.CDLL:
                              ctypes.c_size_t, vp]
     L.bfly_apply_adjoint.restype = ctypes.c_int
     L.bfly_apply_adjoint.argtypes = L.bfly_apply.argtypes
+    L.bfly_apply_noalloc.restype = ctypes.c_int
+    L.bfly_apply_noalloc.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp, i64, ctypes.c_int, ctypes.c_int, vp]
     L.bfly_batch_workspace_size.restype = ctypes.c_int
     L.bfly_batch_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(BatchItem), ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_size_t)]
@@ -128,6 +131,11 @@ def bfly_workspace_size(plan: int, n_in: int, nrhs: int, prec: int) -> int:
 def bfly_apply(plan, n_src, y, g, ldg, n_tgt, x, f, ldf, nrhs, prec, ws, ws_bytes, stream) -> None:
     _check(lib().bfly_apply(plan, n_src, y, g, ldg, n_tgt, x, f, ldf, nrhs, prec, ws, ws_bytes, stream),
            "bfly_apply")
+
+
+def bfly_apply_noalloc(plan, n_src, y, g, ldg, n_tgt, x, f, ldf, nrhs, prec, stream) -> None:
+    _check(lib().bfly_apply_noalloc(plan, n_src, y, g, ldg, n_tgt, x, f, ldf, nrhs, prec, stream),
+           "bfly_apply_noalloc")
 
 
 def bfly_apply_adjoint(plan, n_tgt, x, f_in, ldf, n_src, y, g_out, ldg, nrhs, prec, ws, ws_bytes,
@@ -258,6 +266,25 @@ class Plan:
     def apply(self, y, g, x, prec="fp64", out=None, workspace=None, stream=None):
         """f = B g: sources y (n_src, d), g (nrhs, n_src) -> f (nrhs, n_tgt) at targets x."""
         return self._run(False, y, g, x, prec, out, workspace, stream)
+
+    def apply_noalloc(self, y, g, x, prec="fp64", out=None, stream=None):
+        """f = B g like apply(), with the workspace the library holds on the
+        device (bfly_apply_noalloc): nothing is allocated when `out` is given."""
+        torch = _torch()
+        y = _points(y, self.d, "input points")
+        x = _points(x, self.d, "output points")
+        g, ldg = _values(g, y.shape[0], "input values")
+        nrhs = g.shape[0]
+        if out is None:
+            out = torch.empty((nrhs, x.shape[0]), dtype=torch.complex128, device=y.device)
+        out2, ldf = _values(out, x.shape[0], "output values")
+        if out2.shape[0] != nrhs:
+            raise ValueError("output has the wrong number of right-hand sides")
+        if stream is None:
+            stream = torch.cuda.current_stream(y.device).cuda_stream
+        bfly_apply_noalloc(self.handle, y.shape[0], y.data_ptr(), g.data_ptr(), ldg, x.shape[0], x.data_ptr(),
+                           out2.data_ptr(), ldf, nrhs, _prec_id(prec), stream)
+        return out
 
     def apply_adjoint(self, x, f, y, prec="fp64", out=None, workspace=None, stream=None):
         """g = B' f with B' the butterfly of K^H (roles swapped, phase -Phi)."""

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -136,9 +137,42 @@ int check_sticky() {
   return BFLY_OK;
 }
 
+// ---- workspace of bfly_apply_noalloc ----
+// For callers that cannot allocate device memory: the workspace of an apply
+// lives in this array, one copy per GPU (the runtime places it in each
+// device's memory when the library's code is loaded there; it stays until
+// the process ends).  Host code never uses the array's name as an address:
+// its device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocBytes = BFLY_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(BFLY_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(BFLY_EDEVICE, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(BFLY_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BFLY_OK;
+}
+
+// One apply after host-side validation.  ws == nullptr with noalloc = true
+// takes the workspace from the library's device array (bfly_apply_noalloc).
 int apply_common(bfly_plan_t plan, bool adjoint, int64_t n_in, const double* pin, const void* vin,
                  int64_t ldin, int64_t n_out, const double* pout, void* vout, int64_t ldout, int nrhs,
-                 int prec, void* ws, size_t ws_bytes, void* stream) {
+                 int prec, void* ws, size_t ws_bytes, void* stream, bool noalloc = false) {
   if (int rc = check_plan(plan)) return rc;
   const char* nin = adjoint ? "n_tgt" : "n_src";
   const char* nout = adjoint ? "n_src" : "n_tgt";
@@ -152,6 +186,13 @@ int apply_common(bfly_plan_t plan, bool adjoint, int64_t n_in, const double* pin
   if (n_out > 0 && (!pout || !vout)) return fail(BFLY_EINVAL, "output points or values are NULL");
   Layout L;
   if (int rc = layout(*plan, n_in, nrhs, prec, &L)) return rc;
+  if (noalloc) {
+    if (L.total > kNoAllocBytes)
+      return fail(BFLY_EWORKSPACE, "apply needs %zu bytes of workspace; bfly_apply_noalloc holds at most %zu",
+                  L.total, kNoAllocBytes);
+    if (int rc = scratch_of_current_device(&ws)) return rc;
+    ws_bytes = kNoAllocBytes;
+  }
   if (!ws || ws_bytes < L.total)
     return fail(BFLY_EWORKSPACE, "workspace of %zu bytes given, %zu required", ws ? ws_bytes : (size_t)0,
                 L.total);
@@ -456,6 +497,11 @@ int bfly_apply(bfly_plan_t plan, int64_t n_src, const double* y, const void* g, 
                const double* x, void* f, int64_t ldf, int nrhs, int prec, void* ws, size_t ws_bytes,
                void* stream) {
   return apply_common(plan, false, n_src, y, g, ldg, n_tgt, x, f, ldf, nrhs, prec, ws, ws_bytes, stream);
+}
+
+int bfly_apply_noalloc(bfly_plan_t plan, int64_t n_src, const double* y, const void* g, int64_t ldg, int64_t n_tgt,
+                       const double* x, void* f, int64_t ldf, int nrhs, int prec, void* stream) {
+  return apply_common(plan, false, n_src, y, g, ldg, n_tgt, x, f, ldf, nrhs, prec, nullptr, 0, stream, true);
 }
 
 int bfly_apply_adjoint(bfly_plan_t plan, int64_t n_tgt, const double* x, const void* f_in, int64_t ldf,
