@@ -5,10 +5,13 @@ A step is one full apply (binning, leaf initialisation, the log2 N stages with
 the middle switch, final evaluation) of the 2-D hyperbolic-Radon workload:
 N = 1024 (1,048,576 jittered sources in [1,2) x [0,1), 1,048,576 grid
 targets in [0,1)^2), q = 5 (r = 25), one right-hand side, inputs resident in
-HBM.  Both precision modes are timed; the headline `value` is the FP32 mode,
-the FP64 mode is reported beside it with the speedup.  Relative errors are
-measured against the FP64 CPU oracle (the same run times the oracle on the
-host cores as `cpu_baseline`).
+HBM.  Both precision modes are timed; the headline `value` is the FP64 mode
+(the paper computes in double precision), the FP32 mode is reported beside it
+with the speedup.  Relative errors are measured against the FP64 CPU oracle
+(the same run times the oracle on the host cores as `cpu_baseline`).  Each
+mode carries its roofline: algorithmic flops per launch over the launch's
+event-timed duration against the VALU peak, a sine/cosine evaluation charged
+at the cost the phase-rate microkernel measures in the same run.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -25,19 +28,63 @@ import numpy as np
 METRIC = "Mpoints/s per butterfly apply (2D N=1024, q=5); FP32-MFMA vs FP64 at 1e-5 rel err"
 ROOT = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(ROOT, "paper_1305_4650_amd", "csrc")
-PEAK_VALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, non-packed VALU issue rate
-
-# Flops charged per evaluation of tau (the operations of its definition; sqrt and the
-# sine/cosine pair counted as below).
-SINCOS_FLOPS = 28  # sin + cos pair of a reduced argument (two Horner polynomials)
+# MI355X published vector peaks: FP64 78.6 TFLOP/s (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz), FP32
+# 157.3 TFLOP/s.  The FP32 mode runs its contraction and sine/cosine in FP32 and its phase arguments
+# in FP64; its roofline is taken against the FP32 peak, an FP64 operation counting as two FP32 ones
+# (half the rate).  (The contraction-rate microkernel measures non-packed v_fma_f32 at about 73% of
+# 157.3 on this part, the same fraction FP64 FMAs reach of 78.6, so 78.6 would not bound FP32.)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# Flops charged per evaluation of tau: the operations of its definition, a
+# square root counted as one operation (the kernels' correctly rounded FP64
+# square root takes about ten, and they share it where the definition allows).
 TAU_FLOPS = {"fourier": lambda d: 2 * d - 1, "hypradon2": lambda d: 6, "genradon3": lambda d: 80,
              "genradon3pi": lambda d: 78,
              "separable": lambda d: 5 * d}
+# Harness operations of the phase-rate microkernel per factor (an FP64
+# argument step, two additions into the sum in the working precision), in
+# flops at the precision's own rate, taken off its measured per-factor cost.
+PHASE_RATE_HARNESS_FLOPS = {"fp64": 3, "fp32": 4}
+# FP64 operations (the phase arguments) in flop equivalents of each mode.
+FP64_WEIGHT = {"fp64": 1, "fp32": 2}
 
 
-def phase_flops(phase: str, d: int) -> int:
-    """One phase factor: tau + reduction modulo 1 (2) + sine/cosine pair."""
-    return TAU_FLOPS[phase](d) + 2 + SINCOS_FLOPS
+def affine_x0(prec: str, phase: str, d: int, adjoint: bool) -> bool:
+    """The FP32 kernels factor phases that are affine in the target-role
+    coordinate x0 along node lines (1 + q/2 sine/cosine pairs per line of q
+    factors); FP64 keeps tau's canonical operation order and evaluates every
+    factor."""
+    return prec == "fp32" and (phase == "fourier" or (phase == "hypradon2" and d == 2 and not adjoint))
+
+
+def evaluated(kind: str, prec: str, phase: str, d: int, q: int, adjoint: bool = False):
+    """(sine/cosine evaluations, tau evaluations, factor applications) that
+    the kernels perform per output weight vector of one column-space stage
+    ("col"), row-space stage ("row") or middle switch ("switch"), counted from
+    the kernels' loops.  Where they evaluate every factor, these are the
+    algorithmic counts: column space (2^d + 1) r, row space 2^d r factors of a
+    phase difference and r taus alone, switch r^2 factors and r taus alone.
+    Not modelled (the algorithmic count stands): the hyperbolic-Radon
+    adjoint's factorisations."""
+    r, nc, rm = q ** d, 2 ** d, q ** (d - 1)
+    half = 1 + q // 2
+    aff = affine_x0(prec, phase, d, adjoint)
+    fourier32 = prec == "fp32" and phase == "fourier"
+    if kind == "col":
+        if fourier32:  # per line job: pass 0 two centre factors and q/2 line factors; demodulation 1 + q/2
+            n = (nc // 2) * rm * (2 + q // 2) + rm * half
+            return n, n, (nc + 1) * r
+        return (nc + 1) * r, (nc + 1) * r, (nc + 1) * r
+    if kind == "row":
+        if aff:  # per line job: one tau for the parent centre, per child one tau and 1 + q/2 pairs
+            return rm * nc * half, rm * (nc + 1), nc * r
+        return nc * r, nc * r + r, nc * r
+    if kind == "switch":
+        if phase == "fourier":  # Kronecker product of d q x q factor matrices
+            return d * q * q, d * q * q, d * q ** (d + 1)
+        if aff:  # per line job and source node: one tau and 1 + q/2 pairs
+            return rm * r * half, rm * (r + 1), r * r
+        return r * r, r * r + r, r * r
+    raise ValueError(kind)
 
 
 def tensor_macs(d: int, q: int) -> int:
@@ -47,64 +94,98 @@ def tensor_macs(d: int, q: int) -> int:
     return (2 ** (d + 1) - 2) * q ** (d + 1)
 
 
-def stage_flops(kind: str, phase: str, d: int, N: int, q: int, nrhs: int) -> float:
-    """Algorithmic flops of one merge-and-split stage over all N^d outputs.
-    Column space: (2^d + 1) r phase factors per output vector, each applied
-    to a value (complex multiply, 6 flops per right-hand side).  Row space,
-    on demodulated weights: 2^d r factors of a phase difference (one more
-    flop each) applied by complex multiply-add (8 flops), plus r evaluations
-    of tau alone (the parent-centre phase).  Both: the tensor-form
-    interpolation at 4 flops per real x complex multiply-add."""
-    r, nc, P = q ** d, 2 ** d, N ** d
+def flop_model(prec: str, c_cs: float, phase: str, d: int, N: int, q: int, nrhs: int, n_src: int, n_tgt: int,
+               adjoint: bool = False) -> dict:
+    """Flops charged per unit of work, all N^d output vectors at once: one
+    "stage" of each half, one leaf initialisation, one switch, one final
+    evaluation.  A sine/cosine evaluation costs c_cs (measured: the vector
+    peak over the phase-rate microkernel's factors per second, less its
+    harness), and a phase difference one flop more; tau its TAU_FLOPS (FP64
+    operations, counted twice in the FP32 mode); applying a
+    factor to a complex value 6 flops (complex multiply) or 8 (complex
+    multiply-add, row space and switch); a real x complex multiply-add 4 (the
+    tensor-form interpolation, Sec. 1.4)."""
+    r, P = q ** d, N ** d
+    tf = TAU_FLOPS[phase](d) * FP64_WEIGHT[prec]
     macs = P * tensor_macs(d, q) * nrhs * 4
+
+    def cost(kind, apply_flops, diff):
+        n_cs, n_tau, n_app = evaluated(kind, prec, phase, d, q, adjoint)
+        return P * (n_cs * (c_cs + diff) + n_tau * tf + n_app * nrhs * apply_flops)
+
+    evals_init = n_src + P * r
+    return {
+        "col": cost("col", 6, 0) + macs,
+        "row": cost("row", 8, 1) + macs,
+        "switch": cost("switch", 8, 1),
+        "init": evals_init * (c_cs + tf) + evals_init * nrhs * 6 + n_src * r * nrhs * 4,
+        "final": n_tgt * (c_cs + tf) + n_tgt * r * nrhs * 4 + n_tgt * nrhs * 6,
+    }
+
+
+def kind_flops(kind: str, t: dict, fm: dict) -> float:
+    """Flops of all launches of one kind, from the work counts the library
+    reports for them (stages, initialisations, switches, launches)."""
     if kind == "first":
-        evals = P * (nc + 1) * r
-        return evals * phase_flops(phase, d) + evals * nrhs * 6 + macs
-    evals = P * nc * r
-    return evals * (phase_flops(phase, d) + 1) + P * r * TAU_FLOPS[phase](d) + evals * nrhs * 8 + macs
-
-
-def init_flops(phase, d, N, q, nrhs, n_src):
-    """Leaf initialisation: a phase factor per source point and per leaf node
-    (each applied by complex multiply) and r real x complex multiply-adds per
-    point (the Lagrange weights)."""
-    r, P = q ** d, N ** d
-    evals = n_src + P * r
-    return evals * phase_flops(phase, d) + evals * nrhs * 6 + n_src * r * nrhs * 4
-
-
-def switch_flops(phase, d, N, q, nrhs):
-    """Middle switch: r^2 factors per pair (phase difference, one more flop)
-    applied by complex multiply-add, plus r evaluations of tau alone."""
-    r, P = q ** d, N ** d
-    evals = P * r * r
-    return evals * (phase_flops(phase, d) + 1) + P * r * TAU_FLOPS[phase](d) + evals * nrhs * 8
-
-
-def final_flops(phase, d, N, q, nrhs, n_tgt):
-    """Final evaluation on demodulated weights: one phase factor and r real x
-    complex multiply-adds per target, and the closing complex multiply."""
-    r = q ** d
-    return n_tgt * phase_flops(phase, d) + n_tgt * r * nrhs * 4 + n_tgt * nrhs * 6
-
-
-def kind_flops(kind: str, t: dict, w, n_src: int, n_tgt: int) -> float:
-    """Algorithmic flops of all launches of one kind, from the work counts
-    the library reports for them."""
-    a = (w.phase, w.d, w.N, w.q, w.nrhs)
-    if kind == "first":
-        return (t["stages"] * stage_flops("first", *a) + t["inits"] * init_flops(*a, n_src)
-                + t["switches"] * switch_flops(*a))
+        return t["stages"] * fm["col"] + t["inits"] * fm["init"] + t["switches"] * fm["switch"]
     if kind == "second":
-        return t["stages"] * stage_flops("second", *a)
+        return t["stages"] * fm["row"]
     if kind == "final":
-        return t["launches"] * final_flops(*a, n_tgt)
+        return t["launches"] * fm["final"]
     return 0.0
 
 
-def traffic_per_launch(kernel_family: str):
-    """HBM bytes per launch of a kernel family from the committed counter
-    summary, or None if the kernel sources changed since it was taken."""
+def measure_phase_cost(torch, P, dev) -> dict:
+    """Factors per second of the phase-rate microkernel (the kernels' own
+    reduction and sine/cosine) in each precision, and the per-factor cost in
+    flops at the VALU peak."""
+    from paper_1305_4650_amd import bfly as B
+    n, iters = 256 * 1024 * 4, 256
+    out = torch.empty(n, dtype=torch.complex128, device=dev)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for prec, pid in (("fp64", B.BFLY_FP64), ("fp32", B.BFLY_FP32)):
+        def run():
+            B.bfly_phase_rate(pid, n, iters, 2048.0, out.data_ptr(), stream.cuda_stream)
+        run()
+        torch.cuda.synchronize()
+        ms = time_steps(run, torch, 10, 2)
+        rate = n * iters / (ms * 1e-3)
+        res[prec] = {"factors_per_s": rate, "ms": round(ms, 4),
+                     "c_cs_flops": round(PEAK_TFLOPS[prec] * 1e12 / rate - PHASE_RATE_HARNESS_FLOPS[prec], 2)}
+        print(f"[bench] phase rate {prec}: {rate / 1e9:.0f} G factors/s -> c_cs = "
+              f"{res[prec]['c_cs_flops']:.1f} flops per sine/cosine pair", file=sys.stderr, flush=True)
+    return res
+
+
+def measure_contraction_units(torch, P, dev) -> dict:
+    """FP32 multiply-add rates of the two contraction units (VALU v_fma_f32,
+    matrix cores v_mfma_f32_4x4x1_16b_f32), alone and interleaved in one
+    instruction stream: the measured basis of running the interpolation
+    contractions on the VALU."""
+    from paper_1305_4650_amd import bfly as B
+    n, iters = 256 * 1024 * 2, 2048
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    waves = n // 64
+    macs = {0: 32 * 64, 1: 8 * 256, 2: 32 * 64 + 8 * 256}  # per wave per iteration
+    res = {}
+    for unit, name in ((0, "valu_fma_f32"), (1, "mfma_4x4x1_f32"), (2, "both_interleaved")):
+        ms = time_steps(lambda: B.bfly_contraction_rate(unit, n, iters, out.data_ptr(), stream.cuda_stream), torch,
+                        5, 1)
+        res[name] = {"ms": round(ms, 4), "tflops": round(2 * macs[unit] * waves * iters / (ms * 1e-3) / 1e12, 2)}
+    res["interleaved_over_sum_of_alone"] = round(res["both_interleaved"]["ms"] / (res["valu_fma_f32"]["ms"]
+                                                                                 + res["mfma_4x4x1_f32"]["ms"]), 3)
+    print(f"[bench] contraction units: VALU {res['valu_fma_f32']['tflops']} TFLOP/s, MFMA 4x4x1 "
+          f"{res['mfma_4x4x1_f32']['tflops']} TFLOP/s, interleaved / sum of alone "
+          f"{res['interleaved_over_sum_of_alone']}", file=sys.stderr, flush=True)
+    return res
+
+
+def traffic_per_launch(kernel_family: str, prec: str):
+    """HBM bytes per launch of a kernel family in one precision from the
+    committed counter summary, or None if the kernel sources changed since it
+    was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.json")
     if not os.path.exists(path):
@@ -117,7 +198,7 @@ def traffic_per_launch(kernel_family: str):
             h.update(name.encode() + fh.read())
     if rec.get("source_sha256") != h.hexdigest():
         return None
-    fam = rec.get("kernels", {}).get(kernel_family)
+    fam = rec.get("kernels", {}).get(f"{kernel_family} {prec}")
     return None if fam is None else fam.get("hbm_bytes_per_launch")
 
 
@@ -166,7 +247,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def measure_c5(torch, P, W, dev, steps: int, warmup: int) -> dict:
+def measure_c5(torch, P, W, dev, steps: int, warmup: int, tune: bool = True) -> dict:
     """The uneven batch: 48 hyperbolic-Radon instances (N from {128, 256,
     512, 1024}, q = 5, 8 right-hand sides) in one batched apply, eagerly and
     as a replayed HIP graph, against the 48 applies issued one after another."""
@@ -185,6 +266,15 @@ def measure_c5(torch, P, W, dev, steps: int, warmup: int) -> dict:
     out = {"workload": "48 hyperbolic-Radon instances, N drawn from {128,256,512,1024}, q=5, 8 right-hand sides",
            "instances": len(items), "points_x_rhs": pts, "unit": "Mpoints/s"}
     for prec in ("fp32", "fp64"):
+        if tune:  # one tuning per distinct N (the instances of one N share the key)
+            t0 = time.time()
+            done = set()
+            for (plan, _, y, g, x) in items:
+                if plan.N not in done:
+                    done.add(plan.N)
+                    plan.tune(y, g, x, prec)
+            torch.cuda.synchronize()
+            out[f"tune_s_{prec}"] = round(time.time() - t0, 2)
         batch = P.Batch(items, prec)
         ms_b = time_steps(batch.run, torch, steps, warmup)
         graph = torch.cuda.CUDAGraph()
@@ -216,11 +306,14 @@ def measure_c5(torch, P, W, dev, steps: int, warmup: int) -> dict:
     return out
 
 
-def measure_c4(torch, P, W, dev) -> dict:
+def measure_c4(torch, P, W, dev, nrhs: int = 0) -> dict:
     """The many-right-hand-side Fourier configuration: d = 2, N = 2048, q = 6,
-    64 right-hand sides, one apply per precision (after one warm-up)."""
+    64 right-hand sides (nrhs > 0: only that many, for profiling runs), one
+    apply per precision (after one warm-up)."""
     t0 = time.time()
     w = W.C4()
+    if nrhs > 0:
+        w.g = np.ascontiguousarray(w.g[:nrhs])
     plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
     y, x, g = (torch.from_numpy(a).to(dev) for a in (w.y, w.x, w.g))
     pts = w.N ** 2 * w.nrhs
@@ -329,7 +422,7 @@ def measure_adjoint(torch, P, w, plan, dev, steps: int, cores) -> dict:
     return out
 
 
-def measure_rhs(torch, P, W, dev, steps: int) -> dict:
+def measure_rhs(torch, P, W, dev, steps: int, tune: bool = True) -> dict:
     """The C2 geometry with 8 right-hand sides in one apply (chunks of 2
     share their phase factors), timed with events; reported per right-hand
     side."""
@@ -342,8 +435,12 @@ def measure_rhs(torch, P, W, dev, steps: int) -> dict:
     for prec in ("fp32", "fp64"):
         ws = plan.workspace(w.y.shape[0], w.nrhs, prec, device=dev)
         f = torch.empty((w.nrhs, w.x.shape[0]), dtype=torch.complex128, device=dev)
+        ms_b = time_steps(lambda: plan.apply(y, g, x, prec, out=f, workspace=ws), torch, steps, 2)
+        if tune:
+            plan.tune(y, g, x, prec, out=f, workspace=ws)
         ms = time_steps(lambda: plan.apply(y, g, x, prec, out=f, workspace=ws), torch, steps, 2)
-        out[prec] = {"ms": round(ms, 3), "ms_per_rhs": round(ms / w.nrhs, 4), "value": round(pts / ms / 1e3, 3)}
+        out[prec] = {"ms": round(ms, 3), "ms_per_rhs": round(ms / w.nrhs, 4), "value": round(pts / ms / 1e3, 3),
+                     "builtin_shapes_ms": round(ms_b, 3)}
         print(f"[bench] C2 8 rhs {prec}: {ms:.2f} ms ({ms / w.nrhs:.3f} ms per rhs) -> {pts / ms / 1e3:.1f} Mpoints/s",
               file=sys.stderr, flush=True)
         del ws
@@ -383,11 +480,13 @@ def main() -> int:
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (default: all in affinity)")
     ap.add_argument("--no-c5", action="store_true", help="skip the batched 48-instance measurement")
     ap.add_argument("--no-c4", action="store_true", help="skip the 64-right-hand-side Fourier measurement")
+    ap.add_argument("--c4-rhs", type=int, default=0, help="C4 with only this many right-hand sides (profiling)")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D generalized-Radon measurements")
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse source / target measurements")
     ap.add_argument("--no-c1", action="store_true", help="skip the small (launch-bound) Fourier measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the C2 adjoint measurement")
     ap.add_argument("--no-rhs", action="store_true", help="skip the C2 8-right-hand-side measurement")
+    ap.add_argument("--no-tune", action="store_true", help="time the built-in launch shapes only (no autotuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one plain device copy of 1 GiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -422,6 +521,9 @@ def main() -> int:
     n = w.y.shape[0]
     npts = w.N ** w.d * w.nrhs
 
+    phase_cost = measure_phase_cost(torch, P, dev)
+    units = measure_contraction_units(torch, P, dev)
+    P.bfly_tune_reset()
     res = {}
     for prec in ("fp64", "fp32"):
         ws = plan.workspace(n, w.nrhs, prec, device=dev)
@@ -430,6 +532,14 @@ def main() -> int:
         def step():
             plan.apply(y, g, x, prec, out=f, workspace=ws)
 
+        # built-in launch shapes, then the autotuner's (its time is not in the timed region)
+        ms_builtin = time_steps(step, torch, args.steps, args.warmup)
+        tune_s = None
+        if not args.no_tune:
+            t0 = time.time()
+            plan.tune(y, g, x, prec, out=f, workspace=ws)
+            torch.cuda.synchronize()
+            tune_s = time.time() - t0
         ms = time_steps(step, torch, args.steps, args.warmup)
         dist = time_each(step, torch, 20)
         # instrumented pass: per-step-kind HIP event timing on the apply's stream
@@ -439,9 +549,16 @@ def main() -> int:
             step()
         torch.cuda.synchronize()
         tim = P.bfly_timing_read()
+        recs = P.bfly_timing_launches()
         P.bfly_timing_enable(False)
-        res[prec] = {"ms": ms, "out": f.cpu().numpy(), "timing": tim, "dist": dist}
-        print(f"[bench] {prec}: {ms:.3f} ms/apply  {npts / ms / 1e3:.1f} Mpoints/s  "
+        one = []  # the launches of the first instrumented apply
+        for rec in recs:
+            one.append(rec)
+            if rec["kind"] == "final":
+                break
+        res[prec] = {"ms": ms, "out": f.cpu().numpy(), "timing": tim, "dist": dist, "launches": one,
+                     "builtin_ms": ms_builtin, "tune_s": tune_s}
+        print(f"[bench] {prec}: {ms:.3f} ms/apply  {npts / ms / 1e3:.1f} Mpoints/s (built-in shapes {ms_builtin:.3f} ms) "
               + " ".join(f"{k}={v['ms'] / args.steps:.3f}ms/{v['launches'] // args.steps}"
                          for k, v in tim.items()), file=sys.stderr, flush=True)
         del ws
@@ -474,30 +591,42 @@ def main() -> int:
 
     adj = None if args.no_adjoint else measure_adjoint(
         torch, P, w, plan, dev, 10, None if args.no_cpu_baseline else (args.cpu_threads or len(os.sched_getaffinity(0))))
-    rhs8 = None if args.no_rhs else measure_rhs(torch, P, W, dev, 10)
-    c5 = None if args.no_c5 else measure_c5(torch, P, W, dev, max(3, args.steps // 4), 1)
-    c4 = None if args.no_c4 else measure_c4(torch, P, W, dev)
+    rhs8 = None if args.no_rhs else measure_rhs(torch, P, W, dev, 10, not args.no_tune)
+    c5 = None if args.no_c5 else measure_c5(torch, P, W, dev, max(3, args.steps // 4), 1, not args.no_tune)
+    c4 = None if args.no_c4 else measure_c4(torch, P, W, dev, args.c4_rhs)
     r3d = None if args.no_3d else measure_3d(torch, P, W, dev, 5)
     sparse = None if args.no_sparse else measure_sparse(torch, P, W, dev, 10)
     c1 = None if args.no_c1 else measure_c1(torch, P, W, dev, 200)
 
-    head = "fp32"
-    tim = res[head]["timing"]
-    dom = max(tim, key=lambda k: tim[k]["ms"])
-    launches = max(tim[dom]["launches"], 1)
-    avg_ms = tim[dom]["ms"] / launches
-    flops = kind_flops(dom, tim[dom], w, n, w.x.shape[0]) / launches
-    achieved = flops / (avg_ms * 1e-3) / 1e12
-    fam = {"first": "k_first", "second": "k_second", "final": "k_final"}.get(dom, dom)
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_VALU_TFLOPS, 4), "traffic": traffic_per_launch(fam),
-                "kernel": fam, "avg_launch_ms": round(avg_ms, 5),
-                "algorithmic_flops_per_launch": round(flops)}
-    total_flops = sum(kind_flops(k, tim[k], w, n, w.x.shape[0]) for k in tim)
-    total_s = sum(t["ms"] for t in tim.values()) * 1e-3
-    apply_roofline = {"achieved": round(total_flops / total_s / 1e12, 3),
-                      "frac": round(total_flops / total_s / 1e12 / PEAK_VALU_TFLOPS, 4),
-                      "algorithmic_flops_per_apply": round(total_flops / args.steps)}
+    def roofline_for(prec: str) -> dict:
+        """The dominant launch kind's algorithmic flops per launch over its
+        average event-timed duration, every launch of one apply beside it,
+        and the whole apply."""
+        tim = res[prec]["timing"]
+        fm = flop_model(prec, phase_cost[prec]["c_cs_flops"], w.phase, w.d, w.N, w.q, w.nrhs, n, w.x.shape[0])
+        dom = max(tim, key=lambda k: tim[k]["ms"])
+        launches = max(tim[dom]["launches"], 1)
+        avg_ms = tim[dom]["ms"] / launches
+        flops = kind_flops(dom, tim[dom], fm) / launches
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        fam = {"first": "k_first", "second": "k_second", "final": "k_final"}.get(dom, dom)
+        per = []
+        for rec in res[prec]["launches"]:
+            fl = kind_flops(rec["kind"], dict(rec, launches=1), fm)
+            per.append({"kind": rec["kind"], "stages": rec["stages"], "init": rec["inits"],
+                        "switch": rec["switches"], "ms": round(rec["ms"], 4),
+                        "frac": round(fl / (rec["ms"] * 1e-3) / 1e12 / PEAK_TFLOPS[prec], 4) if fl else None})
+        total_flops = sum(kind_flops(k, tim[k], fm) for k in tim)
+        total_s = sum(t["ms"] for t in tim.values()) * 1e-3
+        return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": traffic_per_launch(fam, prec),
+                "kernel": fam, "avg_launch_ms": round(avg_ms, 5), "algorithmic_flops_per_launch": round(flops),
+                "c_cs_flops": phase_cost[prec]["c_cs_flops"], "launches_of_one_apply": per,
+                "apply": {"achieved": round(total_flops / total_s / 1e12, 3),
+                          "frac": round(total_flops / total_s / 1e12 / PEAK_TFLOPS[prec], 4),
+                          "algorithmic_flops_per_apply": round(total_flops / args.steps)}}
+
+    head = "fp64"
     out = {
         "metric": METRIC,
         "value": round(npts / res[head]["ms"] / 1e3, 3),
@@ -509,7 +638,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "C2: 2-D hyperbolic-Radon phase N*x0*sqrt(y0^2+x1^2*y1^2), N=1024, q=5 (r=25), "
                                "1,048,576 jittered sources in [1,2)x[0,1), 1,048,576 grid targets in [0,1)^2, "
@@ -517,13 +646,19 @@ def main() -> int:
                    "d": w.d, "N": w.N, "q": w.q, "nrhs": w.nrhs, "prec": head,
                    "contraction_unit": "valu"},
         "rel_err_vs_oracle": res[head].get("rel_err"),
-        "fp64": {"value": round(npts / res["fp64"]["ms"] / 1e3, 3), "ms_per_step": round(res["fp64"]["ms"], 4),
-                 "rel_err_vs_oracle": res["fp64"].get("rel_err"), "per_apply": res["fp64"]["dist"]},
         "per_apply": res[head]["dist"],
-        "speedup_fp32_over_fp64": round(res["fp64"]["ms"] / res[head]["ms"], 3),
+        "launch_shapes": "autotuned (bfly_tune) before timing" if not args.no_tune else "built-in",
+        "builtin_shapes_ms": round(res[head]["builtin_ms"], 4),
+        "tune_s": res[head]["tune_s"],
+        "roofline": roofline_for("fp64"),
+        "fp32": {"value": round(npts / res["fp32"]["ms"] / 1e3, 3), "ms_per_step": round(res["fp32"]["ms"], 4),
+                 "rel_err_vs_oracle": res["fp32"].get("rel_err"), "per_apply": res["fp32"]["dist"],
+                 "builtin_shapes_ms": round(res["fp32"]["builtin_ms"], 4), "tune_s": res["fp32"]["tune_s"],
+                 "roofline": roofline_for("fp32")},
+        "speedup_fp32_over_fp64": round(res["fp64"]["ms"] / res["fp32"]["ms"], 3),
         "launch_ms": {p: {k: round(v["ms"] / args.steps, 5) for k, v in res[p]["timing"].items()} for p in res},
-        "roofline": roofline,
-        "apply_roofline_fp32": apply_roofline,
+        "phase_rate": phase_cost,
+        "contraction_units": units,
         "cpu_baseline": cpu,
         "adjoint": adj,
         "c2_8rhs": rhs8,

@@ -230,6 +230,37 @@ int bfly_batch_workspace_size(int n_items, const bfly_batch_item* items, int pre
 int bfly_apply_batched(int n_items, const bfly_batch_item* items, int prec, void* ws, size_t ws_bytes,
                        void* stream);
 
+/* Autotune the launch shapes of one apply: the stages each launch fuses
+ * (every cover of each half of the algorithm by launches the LDS can hold),
+ * the fusion units per workgroup of the column-space and row-space launches,
+ * and whether right-hand sides share phase factors in chunks.  The apply runs
+ * repeatedly on the caller's buffers with candidate shapes, each timed with
+ * HIP events on `stream` (the call synchronises the stream, so it cannot be
+ * captured in a graph); a candidate replaces the best only when 0.5% faster.
+ * The fastest is recorded for (device, d, q, N, nrhs, prec, phase id,
+ * direction), and every later apply with that key uses it (also inside
+ * graphs and batched applies).  Every candidate computes the same result bit
+ * for bit; on return the outputs hold the apply with the chosen shapes.
+ * With BFLY_TUNE_CACHE naming a file, records are read from it at the first
+ * apply and the table is written to it after each tuning; the environment
+ * overrides BFLY_UB, BFLY_KFUSE, BFLY_LDS, BFLY_KSPLIT take precedence over
+ * recorded shapes.
+ *  adjoint              0: the arguments of bfly_apply (inputs g at the
+ *                       sources, outputs f at the targets); 1: those of
+ *                       bfly_apply_adjoint (inputs at the targets)
+ *  n_in .. ld_out, nrhs, prec, ws, ws_bytes, stream   as bfly_apply
+ *  max_ms               stop trying candidates after this much GPU time
+ *                       (>= 0; 0: try all)
+ *  best_ms              (host, may be NULL) the chosen shapes' ms per apply
+ * Returns BFLY_OK, BFLY_EINVAL, BFLY_EWORKSPACE or BFLY_EDEVICE. */
+int bfly_tune(bfly_plan_t plan, int adjoint, int64_t n_in, const double* pts_in, const void* in, int64_t ld_in,
+              int64_t n_out, const double* pts_out, void* out, int64_t ld_out, int nrhs, int prec, void* ws,
+              size_t ws_bytes, double max_ms, double* best_ms, void* stream);
+
+/* Forget every tuned record of this process; with BFLY_TUNE_CACHE set, the
+ * next apply reads the file's records again.  Returns BFLY_OK. */
+int bfly_tune_reset(void);
+
 /* Per-step timing, for profiling.  While enabled, every apply records a HIP
  * event pair around each kernel launch on its stream (a few microseconds of
  * overhead per launch).  bfly_timing_read waits for the recorded events and
@@ -247,6 +278,39 @@ int bfly_apply_batched(int n_items, const bfly_batch_item* items, int prec, void
 enum { BFLY_NUM_STEPS = 4 };
 int bfly_timing_enable(int on);
 int bfly_timing_read(double* ms, int64_t* launches, int64_t* stages, int64_t* inits, int64_t* switches);
+
+/* The launches that the last bfly_timing_read collected, one record each in
+ * launch order: kind (BFLY_STEP_*), merge-and-split stages, leaf
+ * initialisations and middle switches it performed, and its milliseconds.
+ * Writes min(cap, total) records into the host arrays (each of cap entries)
+ * and the total into *count.  Returns BFLY_OK or BFLY_EINVAL. */
+int bfly_timing_launches(int cap, int* count, int* kind, int* stages, int* inits, int* switches, double* ms);
+
+/* Phase-factor throughput, for the roofline accounting of an apply: each of
+ * n_threads threads evaluates `iters` factors exp(2 pi i tau) with the
+ * reduction and sine/cosine that the apply's kernels use in precision prec
+ * (BFLY_FP64 or BFLY_FP32), at arguments spread over [0, span) turns, and
+ * writes the sum of its factors to out[thread] (device complex128
+ * [n_threads]).  The paper evaluates these factors in batches and they are
+ * the bulk of the work (Sec. 3); timing this call (events around it on
+ * `stream`) gives the cost of one factor.  Besides each factor the kernel
+ * does three FP64 additions per factor (argument step and the sum).
+ *  n_threads  1 .. 2^30;  iters  a positive multiple of 8;  0 <= span < 1e15
+ * Enqueues one kernel; no allocation.  Returns BFLY_OK, BFLY_EINVAL or
+ * BFLY_EDEVICE. */
+int bfly_phase_rate(int prec, int64_t n_threads, int64_t iters, double span, void* out, void* stream);
+
+/* FP32 multiply-add throughput of the two contraction units, for the choice
+ * between them: unit 0 runs 32 independent v_fma_f32 chains per lane (VALU),
+ * unit 1 eight independent v_mfma_f32_4x4x1_16b_f32 chains per wave (matrix
+ * cores: 16 blocks of 4 x 4 x 1, 256 multiply-adds per instruction), unit 2
+ * both in one instruction stream (per iteration 8 matrix instructions and
+ * 32 vector multiply-adds per lane).  Each of n_threads threads (a multiple
+ * of 64) runs `iters` iterations and writes one sum to out[thread] (device
+ * float [n_threads]).  Per iteration a wave does 32 x 64 (unit 0), 8 x 256
+ * (unit 1) or both (unit 2) multiply-adds.  Time the call with events on
+ * `stream`.  Returns BFLY_OK, BFLY_EINVAL or BFLY_EDEVICE. */
+int bfly_contraction_rate(int unit, int64_t n_threads, int64_t iters, void* out, void* stream);
 
 /* Static description of a status code. */
 const char* bfly_status_string(int status);

@@ -9,8 +9,9 @@ workloads (``workloads.py``).
 """
 from .bfly import (BFLY_FP32, BFLY_FP64, Batch, BatchItem, BflyError, Plan, apply_batched,  # noqa: F401
                    bfly_apply, bfly_apply_adjoint, bfly_apply_autograd, bfly_apply_batched,
-                   bfly_apply_batched_autograd, bfly_batch_workspace_size, bfly_last_error, bfly_plan,
-                   bfly_plan_destroy, bfly_plan_info, bfly_status_string, bfly_timing_enable, bfly_timing_read,
+                   bfly_apply_batched_autograd, bfly_batch_workspace_size, bfly_contraction_rate, bfly_last_error,
+                   bfly_phase_rate, bfly_plan, bfly_plan_destroy, bfly_plan_info, bfly_status_string,
+                   bfly_timing_enable, bfly_timing_launches, bfly_timing_read, bfly_tune, bfly_tune_reset,
                    bfly_workspace_size, lib)
 
 

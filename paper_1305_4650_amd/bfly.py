@@ -27,7 +27,9 @@ PRECISIONS = {"fp64": BFLY_FP64, "fp32": BFLY_FP32, "split32": BFLY_SPLIT32}
 
 EXPORTS = ("bfly_plan", "bfly_plan_destroy", "bfly_plan_info", "bfly_workspace_size", "bfly_apply",
            "bfly_apply_noalloc", "bfly_apply_adjoint", "bfly_batch_workspace_size", "bfly_apply_batched",
-           "bfly_timing_enable", "bfly_timing_read", "bfly_status_string", "bfly_last_error")
+           "bfly_tune", "bfly_tune_reset", "bfly_timing_enable", "bfly_timing_read", "bfly_timing_launches",
+           "bfly_phase_rate", "bfly_contraction_rate",
+           "bfly_status_string", "bfly_last_error")
 STEP_NAMES = ("binning", "first", "second", "final")
 
 
@@ -83,6 +85,18 @@ def lib() -> ctypes.CDLL:
     L.bfly_timing_enable.argtypes = [ctypes.c_int]
     L.bfly_timing_read.restype = ctypes.c_int
     L.bfly_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double)] + [ctypes.POINTER(i64)] * 4
+    L.bfly_tune.restype = ctypes.c_int
+    L.bfly_tune.argtypes = [vp, ctypes.c_int, i64, vp, vp, i64, i64, vp, vp, i64, ctypes.c_int, ctypes.c_int, vp,
+                            ctypes.c_size_t, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+    L.bfly_tune_reset.restype = ctypes.c_int
+    L.bfly_tune_reset.argtypes = []
+    L.bfly_timing_launches.restype = ctypes.c_int
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.bfly_timing_launches.argtypes = [ctypes.c_int, ip, ip, ip, ip, ip, ctypes.POINTER(ctypes.c_double)]
+    L.bfly_phase_rate.restype = ctypes.c_int
+    L.bfly_phase_rate.argtypes = [ctypes.c_int, i64, i64, ctypes.c_double, vp, vp]
+    L.bfly_contraction_rate.restype = ctypes.c_int
+    L.bfly_contraction_rate.argtypes = [ctypes.c_int, i64, i64, vp, vp]
     L.bfly_status_string.restype = ctypes.c_char_p
     L.bfly_status_string.argtypes = [ctypes.c_int]
     L.bfly_last_error.restype = ctypes.c_char_p
@@ -155,6 +169,19 @@ def bfly_apply_batched(items, prec: int, ws, ws_bytes, stream) -> None:
     _check(lib().bfly_apply_batched(len(items), items, prec, ws, ws_bytes, stream), "bfly_apply_batched")
 
 
+def bfly_tune(plan, adjoint, n_in, pts_in, vin, ld_in, n_out, pts_out, vout, ld_out, nrhs, prec, ws, ws_bytes,
+              max_ms, stream) -> float:
+    """Autotune one apply's launch shapes; returns the chosen shapes' ms per apply."""
+    best = ctypes.c_double()
+    _check(lib().bfly_tune(plan, int(adjoint), n_in, pts_in, vin, ld_in, n_out, pts_out, vout, ld_out, nrhs, prec,
+                           ws, ws_bytes, max_ms, ctypes.byref(best), stream), "bfly_tune")
+    return best.value
+
+
+def bfly_tune_reset() -> None:
+    _check(lib().bfly_tune_reset(), "bfly_tune_reset")
+
+
 def bfly_timing_enable(on: bool) -> None:
     _check(lib().bfly_timing_enable(int(bool(on))), "bfly_timing_enable")
 
@@ -166,6 +193,25 @@ def bfly_timing_read() -> dict:
     _check(lib().bfly_timing_read(ms, *cnt), "bfly_timing_read")
     return {k: {"ms": ms[i], "launches": cnt[0][i], "stages": cnt[1][i], "inits": cnt[2][i],
                 "switches": cnt[3][i]} for i, k in enumerate(STEP_NAMES)}
+
+
+def bfly_timing_launches(cap: int = 4096) -> list:
+    """[{"kind", "stages", "inits", "switches", "ms"}] of the launches the last
+    bfly_timing_read collected, in launch order."""
+    cnt = ctypes.c_int()
+    arr = [(ctypes.c_int * cap)() for _ in range(4)]
+    ms = (ctypes.c_double * cap)()
+    _check(lib().bfly_timing_launches(cap, ctypes.byref(cnt), *arr, ms), "bfly_timing_launches")
+    return [{"kind": STEP_NAMES[arr[0][i]], "stages": arr[1][i], "inits": arr[2][i], "switches": arr[3][i],
+             "ms": ms[i]} for i in range(min(cnt.value, cap))]
+
+
+def bfly_phase_rate(prec: int, n_threads: int, iters: int, span: float, out, stream) -> None:
+    _check(lib().bfly_phase_rate(prec, n_threads, iters, span, out, stream), "bfly_phase_rate")
+
+
+def bfly_contraction_rate(unit: int, n_threads: int, iters: int, out, stream) -> None:
+    _check(lib().bfly_contraction_rate(unit, n_threads, iters, out, stream), "bfly_contraction_rate")
 
 
 def bfly_status_string(status: int) -> str:
@@ -262,6 +308,30 @@ class Plan:
         fn(self.handle, n_in, pin.data_ptr(), vin.data_ptr(), ldin, n_out, pout.data_ptr(),
            out2.data_ptr(), ldout, nrhs, p, workspace.data_ptr(), workspace.numel(), stream)
         return out
+
+    def tune(self, pin, vin, pout, prec="fp64", adjoint=False, max_ms=0.0, out=None, workspace=None, stream=None):
+        """Autotune the launch shapes of apply (adjoint=False: pin = sources,
+        vin = g, pout = targets) or apply_adjoint (pin = targets) on these
+        buffers (bfly_tune); later applies with the same key use the result.
+        Returns (outputs of the apply with the chosen shapes, ms per apply)."""
+        torch = _torch()
+        pin = _points(pin, self.d, "input points")
+        pout = _points(pout, self.d, "output points")
+        vin, ldin = _values(vin, pin.shape[0], "input values")
+        nrhs = vin.shape[0]
+        p = _prec_id(prec)
+        if out is None:
+            out = torch.empty((nrhs, pout.shape[0]), dtype=torch.complex128, device=pin.device)
+        out2, ldout = _values(out, pout.shape[0], "output values")
+        if workspace is None:
+            workspace = torch.empty(max(self.workspace_size(pin.shape[0], nrhs, p), 1), dtype=torch.uint8,
+                                    device=pin.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(pin.device).cuda_stream
+        ms = bfly_tune(self.handle, adjoint, pin.shape[0], pin.data_ptr(), vin.data_ptr(), ldin, pout.shape[0],
+                       pout.data_ptr(), out2.data_ptr(), ldout, nrhs, p, workspace.data_ptr(), workspace.numel(),
+                       float(max_ms), stream)
+        return out, ms
 
     def apply(self, y, g, x, prec="fp64", out=None, workspace=None, stream=None):
         """f = B g: sources y (n_src, d), g (nrhs, n_src) -> f (nrhs, n_tgt) at targets x."""

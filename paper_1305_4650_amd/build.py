@@ -31,7 +31,7 @@ COMMON = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
 SOURCES = ["bfly_d2.hip", "bfly_d2_batch.hip", "bfly_d3.hip", "bfly_d3_batch.hip", "bfly_d1.hip",
-           "bfly_d1_batch.hip", "bfly_common.hip", "bfly_api.cpp", "bfly_timing.cpp"]
+           "bfly_d1_batch.hip", "bfly_common.hip", "bfly_api.cpp", "bfly_timing.cpp", "bfly_phase.hip", "bfly_tune.cpp"]
 
 
 def build(verbose: bool = True, jobs: int = 6, out: str = LIB, defines=(), build_dir: str = BUILD) -> str:

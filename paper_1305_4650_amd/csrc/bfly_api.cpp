@@ -1,5 +1,6 @@
 // Host side of libbfly: argument validation (before any HIP call), plans,
 // workspace sizing and carving, and the C ABI of include/bfly.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -128,6 +129,23 @@ int check_plan(const bfly_plan_s* p) {
   return BFLY_OK;
 }
 
+// The workspace of one apply, carved into its pieces.
+bfly::Work carve(const bfly_plan_s& p, const Layout& L, void* ws) {
+  char* base = static_cast<char*>(ws);
+  bfly::Work w;
+  w.W = base + L.w;
+  w.keys = reinterpret_cast<uint32_t*>(base + L.keys);
+  w.keys_sorted = reinterpret_cast<uint32_t*>(base + L.keys_sorted);
+  w.idx = nullptr;
+  w.perm = reinterpret_cast<int32_t*>(base + L.perm);
+  w.offs = reinterpret_cast<int32_t*>(base + L.offs);
+  w.empty = w.offs + ((int64_t)1 << (p.d * p.L)) + 1;
+  w.tocc = reinterpret_cast<uint8_t*>(base + L.tocc);
+  w.sort_tmp = base + L.tmp;
+  w.sort_tmp_bytes = L.tmp_bytes;
+  return w;
+}
+
 int check_sticky() {
   hipError_t e = hipPeekAtLastError();
   if (e != hipSuccess) {
@@ -198,22 +216,149 @@ int apply_common(bfly_plan_t plan, bool adjoint, int64_t n_in, const double* pin
                 L.total);
   if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(BFLY_EINVAL, "workspace must be 256-byte aligned");
   if (int rc = check_sticky()) return rc;
-  char* base = static_cast<char*>(ws);
-  bfly::Work w;
-  w.W = base + L.w;
-  w.keys = reinterpret_cast<uint32_t*>(base + L.keys);
-  w.keys_sorted = reinterpret_cast<uint32_t*>(base + L.keys_sorted);
-  w.idx = nullptr;
-  w.perm = reinterpret_cast<int32_t*>(base + L.perm);
-  w.offs = reinterpret_cast<int32_t*>(base + L.offs);
-  w.empty = w.offs + ((int64_t)1 << (plan->d * plan->L)) + 1;
-  w.tocc = reinterpret_cast<uint8_t*>(base + L.tocc);
-  w.sort_tmp = base + L.tmp;
-  w.sort_tmp_bytes = L.tmp_bytes;
+  bfly::Work w = carve(*plan, L, ws);
   bfly::Geo g = make_geo(*plan, adjoint);
   hipError_t e = bfly::run_apply(g, prec, n_in, pin, static_cast<const double*>(vin), ldin, n_out, pout,
                                  static_cast<double*>(vout), ldout, nrhs, w, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(BFLY_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+// ---- autotuning (bfly_tune) ----
+
+// All ways of covering n stages by launches of 1..kmax stages each.
+void compositions(int n, int kmax, std::vector<int>& cur, std::vector<std::vector<int>>& out) {
+  if (n == 0) {
+    out.push_back(cur);
+    return;
+  }
+  for (int k = 1; k <= std::min(n, kmax); ++k) {
+    cur.push_back(k);
+    compositions(n - k, kmax, cur, out);
+    cur.pop_back();
+  }
+}
+
+// The greedy cover: launches of kmax stages, the last one shorter.
+std::vector<int> greedy(int n, int kmax) {
+  std::vector<int> v;
+  for (int l = 0; l < n; l += kmax) v.push_back(std::min(kmax, n - l));
+  return v;
+}
+
+bfly::TuneParams with_split(bfly::TuneParams p, const std::vector<int>& a, const std::vector<int>& b) {
+  p.nsplit = 0;
+  for (int k : a)
+    if (p.nsplit < 16) p.split[p.nsplit++] = k;
+  for (int k : b)
+    if (p.nsplit < 16) p.split[p.nsplit++] = k;
+  return p;
+}
+
+int tune_common(bfly_plan_t plan, int adjoint, int64_t n_in, const double* pin, const void* vin, int64_t ldin,
+                int64_t n_out, const double* pout, void* vout, int64_t ldout, int nrhs, int prec, void* ws,
+                size_t ws_bytes, double max_ms, double* best_ms, void* stream) {
+  if (adjoint != 0 && adjoint != 1) return fail(BFLY_EINVAL, "adjoint must be 0 or 1");
+  if (!(max_ms >= 0.0)) return fail(BFLY_EINVAL, "max_ms must be >= 0");
+  // validation and one apply with the current shapes (also a warm-up)
+  if (int rc = apply_common(plan, adjoint != 0, n_in, pin, vin, ldin, n_out, pout, vout, ldout, nrhs, prec, ws,
+                            ws_bytes, stream))
+    return rc;
+  Layout L;
+  if (int rc = layout(*plan, n_in, nrhs, prec, &L)) return rc;
+  const bfly::Work w = carve(*plan, L, ws);
+  const bfly::Geo g = make_geo(*plan, adjoint != 0);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  bfly::ShapeLimits lim;
+  hipError_t e = bfly::shape_limits(g, prec, &lim);
+  if (e != hipSuccess) return fail(BFLY_EDEVICE, "shape query failed: %s", hipGetErrorString(e));
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess) {
+    if (ev0) (void)hipEventDestroy(ev0);
+    return fail(BFLY_EDEVICE, "hipEventCreate failed");
+  }
+  double spent = 0.0;
+  int reps = 3;
+  // time per apply of one candidate (a warm-up apply, then reps applies)
+  auto measure = [&](const bfly::TuneParams& p, double* ms) -> hipError_t {
+    hipError_t err = bfly::run_apply(g, prec, n_in, pin, static_cast<const double*>(vin), ldin, n_out, pout,
+                                     static_cast<double*>(vout), ldout, nrhs, w, st, &p);
+    if (err == hipSuccess) err = hipEventRecord(ev0, st);
+    for (int i = 0; i < reps && err == hipSuccess; ++i)
+      err = bfly::run_apply(g, prec, n_in, pin, static_cast<const double*>(vin), ldin, n_out, pout,
+                            static_cast<double*>(vout), ldout, nrhs, w, st, &p);
+    if (err == hipSuccess) err = hipEventRecord(ev1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(ev1);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, ev0, ev1);
+    *ms = (double)t / reps;
+    spent += (double)t * (reps + 1) / reps;
+    return err;
+  };
+  bfly::TuneParams best;  // all zero: the built-in shapes
+  double best_t = 0.0;
+  e = measure(best, &best_t);
+  if (e == hipSuccess && best_t < 1.0) {  // short applies: more repetitions against timer noise
+    reps = 10;
+    e = measure(best, &best_t);
+  }
+  // a candidate replaces the best only if it is faster by more than the noise
+  auto consider = [&](const bfly::TuneParams& p) {
+    if (e != hipSuccess || (max_ms > 0.0 && spent >= max_ms)) return;
+    double t = 0.0;
+    e = measure(p, &t);
+    if (e == hipSuccess && t < best_t * 0.995) {
+      best = p;
+      best_t = t;
+    }
+  };
+  const bool chunked = lim.rc > 1 && nrhs >= lim.rc;
+  const int kmax = chunked ? lim.kmax_rc : lim.kmax_one;
+  if (g.ls > 0) {
+    // stages per launch: every cover of the column-space half with the
+    // built-in row-space cover, then every cover of the row-space half with
+    // the best column-space one (the built-in covers take launches of kcol /
+    // krow stages, the last shorter)
+    std::vector<std::vector<int>> col, row;
+    std::vector<int> cur;
+    compositions(g.ls, kmax, cur, col);
+    compositions(g.L - g.ls, kmax, cur, row);
+    std::vector<int> col_best = greedy(g.ls, chunked ? lim.kcol_rc : lim.kcol_one);
+    const std::vector<int> row0 = greedy(g.L - g.ls, chunked ? lim.krow_rc : lim.krow_one);
+    for (const auto& c : col) {
+      const double before = best_t;
+      consider(with_split(best, c, row0));
+      if (best_t < before) col_best = c;
+    }
+    for (const auto& r : row) consider(with_split(best, col_best, r));
+  }
+  // units per workgroup block, per launch kind
+  for (int ub : {1, 2, 3, 4, 6, 8}) {
+    bfly::TuneParams p = best;
+    p.ub_first = ub;
+    consider(p);
+  }
+  for (int ub : {1, 2, 3, 4, 6, 8}) {
+    bfly::TuneParams p = best;
+    p.ub_second = ub;
+    consider(p);
+  }
+  // one right-hand side per workgroup instead of chunks
+  if (lim.rc > 1 && nrhs >= lim.rc) {
+    bfly::TuneParams p = best;
+    p.rc_one = 1;
+    consider(p);
+  }
+  // leave the chosen shapes' result in the outputs
+  if (e == hipSuccess)
+    e = bfly::run_apply(g, prec, n_in, pin, static_cast<const double*>(vin), ldin, n_out, pout,
+                        static_cast<double*>(vout), ldout, nrhs, w, st, &best);
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  if (e != hipSuccess) return fail(BFLY_EDEVICE, "tuning run failed: %s", hipGetErrorString(e));
+  e = bfly::tune_store(g, nrhs, prec, best, best_t);
+  if (e != hipSuccess) return fail(BFLY_EINVAL, "could not write the tuning cache (BFLY_TUNE_CACHE)");
+  if (best_ms) *best_ms = best_t;
   return ok();
 }
 
@@ -523,6 +668,18 @@ int bfly_apply_batched(int n_items, const bfly_batch_item* items, int prec, void
   return apply_batched(n_items, items, prec, ws, ws_bytes, stream);
 }
 
+int bfly_tune(bfly_plan_t plan, int adjoint, int64_t n_in, const double* pts_in, const void* in, int64_t ld_in,
+              int64_t n_out, const double* pts_out, void* out, int64_t ld_out, int nrhs, int prec, void* ws,
+              size_t ws_bytes, double max_ms, double* best_ms, void* stream) {
+  return tune_common(plan, adjoint, n_in, pts_in, in, ld_in, n_out, pts_out, out, ld_out, nrhs, prec, ws, ws_bytes,
+                     max_ms, best_ms, stream);
+}
+
+int bfly_tune_reset(void) {
+  bfly::tune_clear();
+  return ok();
+}
+
 int bfly_timing_enable(int on) {
   bfly::timing_set(on != 0);
   return ok();
@@ -532,6 +689,22 @@ int bfly_timing_read(double* ms, int64_t* launches, int64_t* stages, int64_t* in
   if (!ms || !launches || !stages || !inits || !switches) return fail(BFLY_EINVAL, "output arrays are NULL");
   hipError_t e = bfly::timing_read(ms, launches, stages, inits, switches);
   if (e != hipSuccess) return fail(BFLY_EDEVICE, "timing events failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+int bfly_timing_launches(int cap, int* count, int* kind, int* stages, int* inits, int* switches, double* ms) {
+  if (cap < 0 || !count) return fail(BFLY_EINVAL, "cap < 0 or count is NULL");
+  if (cap > 0 && (!kind || !stages || !inits || !switches || !ms)) return fail(BFLY_EINVAL, "output arrays are NULL");
+  std::vector<bfly::LaunchRecord> rec((size_t)cap);
+  const int n = bfly::timing_launches(cap, rec.data());
+  for (int i = 0; i < n && i < cap; ++i) {
+    kind[i] = rec[i].kind;
+    stages[i] = rec[i].stages;
+    inits[i] = rec[i].inits;
+    switches[i] = rec[i].switches;
+    ms[i] = rec[i].ms;
+  }
+  *count = n;
   return ok();
 }
 

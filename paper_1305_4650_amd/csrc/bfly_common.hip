@@ -485,8 +485,10 @@ void tune_from_env(LevelArgs& la) {
     }
     return v;
   }();
-  la.nsplit = (int)split.size();
-  for (int i = 0; i < la.nsplit; ++i) la.split[i] = split[i];
+  if (!split.empty()) {
+    la.nsplit = (int)split.size();
+    for (int i = 0; i < la.nsplit; ++i) la.split[i] = split[i];
+  }
 }
 
 }  // namespace
@@ -565,9 +567,14 @@ size_t tocc_bytes(int d, int L) {
   return (b + 3) & ~(size_t)3;
 }
 
+hipError_t shape_limits(const Geo& g, int prec, ShapeLimits* out) {
+  return g.d == 1 ? shape_limits_d1(g, prec, out)
+                  : (g.d == 2 ? shape_limits_d2(g, prec, out) : shape_limits_d3(g, prec, out));
+}
+
 hipError_t run_apply(const Geo& g, int prec, int64_t n_in, const double* pts_in, const double* vals_in,
                      int64_t ld_in, int64_t n_out, const double* pts_out, double* vals_out, int64_t ld_out,
-                     int nrhs, const Work& w, hipStream_t st) {
+                     int nrhs, const Work& w, hipStream_t st, const TuneParams* force) {
   const hipError_t e = g.d == 1 ? bin_sources<1>(g, n_in, pts_in, w, st)
                                 : (g.d == 2 ? bin_sources<2>(g, n_in, pts_in, w, st)
                                             : bin_sources<3>(g, n_in, pts_in, w, st));
@@ -604,6 +611,15 @@ hipError_t run_apply(const Geo& g, int prec, int64_t n_in, const double* pts_in,
   la.vals_out = vals_out;
   la.ld_out = ld_out;
   la.stream = st;
+  TuneParams tp;
+  if (force || tune_lookup(g, nrhs, prec, &tp)) {
+    const TuneParams& t = force ? *force : tp;
+    la.ub_first = t.ub_first;
+    la.ub_second = t.ub_second;
+    la.rc_one = t.rc_one;
+    la.nsplit = std::min(t.nsplit, 16);
+    for (int i = 0; i < la.nsplit; ++i) la.split[i] = t.split[i];
+  }
   tune_from_env(la);
   switch (g.d) {
     case 1:

@@ -67,6 +67,14 @@ class StepTimer {
   hipEvent_t b_ = nullptr;
 };
 bool timing_on();
+// One timed launch: its kind, the work it performed, its duration.
+struct LaunchRecord {
+  int kind, stages, inits, switches;
+  double ms;
+};
+// Copies up to cap records of the launches collected by the last
+// timing_read, in launch order; returns how many there are.
+int timing_launches(int cap, LaunchRecord* out);
 hipError_t timing_read(double* ms, int64_t* launches, int64_t* stages, int64_t* inits, int64_t* switches);
 void timing_set(bool on);
 
@@ -96,7 +104,9 @@ struct LevelArgs {
   double* vals_out = nullptr;
   int64_t ld_out = 0;
   hipStream_t stream = nullptr;
-  int ub_force = 0;              // fusion units per workgroup block (0: chosen per launch)
+  int ub_force = 0;              // fusion units per workgroup block, every launch (0: see below)
+  int ub_first = 0, ub_second = 0;  // per launch kind (0: chosen per launch)
+  int rc_one = 0;                // 1: one right-hand side per workgroup (no chunks)
   int k_fuse = 0;                // merge-and-split stages fused per launch, at most (0: by shape)
   // tuning override: stages of each launch, column-space launches then
   // row-space ones (used only when they add up to each half and fit the LDS)
@@ -104,6 +114,34 @@ struct LevelArgs {
   int nsplit = 0;
   size_t lds_budget = 81920;     // bytes of LDS per workgroup (two workgroups per CU)
 };
+// Launch-shape limits of one (d, q, phase, precision): the right-hand-side
+// chunk of its kernels and the most stages a launch can fuse with chunks
+// and with one right-hand side per workgroup.
+struct ShapeLimits {
+  int rc = 1, kmax_rc = 1, kmax_one = 1;
+  // built-in stages per launch of the column-space and row-space halves
+  int kcol_rc = 1, krow_rc = 1, kcol_one = 1, krow_one = 1;
+};
+hipError_t shape_limits(const Geo& g, int prec, ShapeLimits* out);
+hipError_t shape_limits_d1(const Geo& g, int prec, ShapeLimits* out);
+hipError_t shape_limits_d2(const Geo& g, int prec, ShapeLimits* out);
+hipError_t shape_limits_d3(const Geo& g, int prec, ShapeLimits* out);
+
+// Launch shapes of one apply chosen by the autotuner (bfly_tune); zero
+// fields keep the built-in choice.
+struct TuneParams {
+  int ub_first = 0, ub_second = 0, rc_one = 0, nsplit = 0;
+  int split[16] = {0};
+};
+// Tuned shapes for (current device, geometry, nrhs, precision): true and *p
+// filled if there is a record.  The first call loads BFLY_TUNE_CACHE.
+bool tune_lookup(const Geo& g, int nrhs, int prec, TuneParams* p);
+// Record tuned shapes (and write BFLY_TUNE_CACHE if set); ms is the time
+// per apply that was measured with them.
+hipError_t tune_store(const Geo& g, int nrhs, int prec, const TuneParams& p, double ms);
+// Forget every record (tests).
+void tune_clear();
+
 hipError_t run_levels_d1(const LevelArgs& la, int prec);
 hipError_t run_levels_d2(const LevelArgs& la, int prec);
 hipError_t run_levels_d3(const LevelArgs& la, int prec);
@@ -177,9 +215,12 @@ void tune_batch_from_env(BatchGroup& bg);
 
 // Enqueue one apply (binning, initialisation, stages, switch, final
 // evaluation) on `stream`.  Inputs were validated by the caller.
+// `force` (may be null) gives the launch shapes to use; otherwise the
+// tuning table's record for this apply, if any, else the built-in choice.
+// BFLY_UB / BFLY_KFUSE / BFLY_LDS / BFLY_KSPLIT override both.
 hipError_t run_apply(const Geo& g, int prec, int64_t n_in, const double* pts_in,
                      const double* vals_in, int64_t ld_in, int64_t n_out,
                      const double* pts_out, double* vals_out, int64_t ld_out, int nrhs,
-                     const Work& w, hipStream_t stream);
+                     const Work& w, hipStream_t stream, const TuneParams* force = nullptr);
 
 }  // namespace bfly

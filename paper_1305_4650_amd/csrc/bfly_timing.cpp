@@ -20,6 +20,7 @@ struct State {
   std::vector<hipEvent_t> pool;
   double ms[kNumSteps] = {};
   int64_t launches[kNumSteps] = {}, stages[kNumSteps] = {}, inits[kNumSteps] = {}, switches[kNumSteps] = {};
+  std::vector<LaunchRecord> log;  // the launches the last timing_read collected, in order
 };
 
 State& st() {
@@ -74,6 +75,7 @@ hipError_t timing_read(double* ms, int64_t* launches, int64_t* stages, int64_t* 
   State& S = st();
   std::lock_guard<std::mutex> lk(S.mu);
   hipError_t err = hipSuccess;
+  S.log.clear();
   for (const Pending& p : S.pending) {
     hipError_t e = hipEventSynchronize(p.e);
     float t = 0.f;
@@ -86,6 +88,7 @@ hipError_t timing_read(double* ms, int64_t* launches, int64_t* stages, int64_t* 
       S.stages[p.kind] += p.stages;
       S.inits[p.kind] += p.inits;
       S.switches[p.kind] += p.switches;
+      S.log.push_back({p.kind, p.stages, p.inits, p.switches, (double)t});
     }
     S.pool.push_back(p.b);
     S.pool.push_back(p.e);
@@ -101,6 +104,14 @@ hipError_t timing_read(double* ms, int64_t* launches, int64_t* stages, int64_t* 
     S.launches[k] = S.stages[k] = S.inits[k] = S.switches[k] = 0;
   }
   return err;
+}
+
+int timing_launches(int cap, LaunchRecord* out) {
+  State& S = st();
+  std::lock_guard<std::mutex> lk(S.mu);
+  const int n = (int)S.log.size();
+  for (int i = 0; i < n && i < cap; ++i) out[i] = S.log[i];
+  return n;
 }
 
 }  // namespace bfly

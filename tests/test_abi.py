@@ -211,3 +211,24 @@ def test_batch_item_layout_matches_header():
     """The ctypes mirror of bfly_batch_item has the C layout (LP64)."""
     assert ctypes.sizeof(B.BatchItem) == 80
     assert B.BatchItem.n_in.offset == 16 and B.BatchItem.ld_out.offset == 72
+
+
+def test_tune_rejects_invalid_arguments_on_host():
+    """bfly_tune validates like bfly_apply before any HIP call."""
+    p = P.Plan(2, 16, BOX2, TBOX2, "hypradon2", 4)
+    L = B.lib()
+    fake = ctypes.c_void_p(0x1000)
+    best = ctypes.c_double()
+
+    def call(adjoint=0, nrhs=1, prec=0, max_ms=0.0, ws_bytes=1 << 30, plan=p.handle):
+        return L.bfly_tune(plan, adjoint, 256, fake, fake, 256, 256, fake, fake, 256, nrhs, prec, fake, ws_bytes,
+                           max_ms, ctypes.byref(best), None)
+
+    assert call(adjoint=2) == B.BFLY_EINVAL
+    assert call(max_ms=-1.0) == B.BFLY_EINVAL
+    assert call(nrhs=0) == B.BFLY_EINVAL
+    assert call(prec=7) == B.BFLY_EINVAL
+    assert call(prec=B.BFLY_SPLIT32) == B.BFLY_EUNSUPPORTED
+    assert call(ws_bytes=16) == B.BFLY_EWORKSPACE
+    assert call(plan=None) == B.BFLY_EINVAL
+    assert L.bfly_tune_reset() == B.BFLY_OK
