@@ -75,6 +75,8 @@ def evaluated(kind: str, prec: str, phase: str, d: int, q: int, adjoint: bool = 
             return n, n, (nc + 1) * r
         return (nc + 1) * r, (nc + 1) * r, (nc + 1) * r
     if kind == "row":
+        if fourier32:  # per line job: q/2 line factors shared by the children (conjugate), one per child
+            return rm * (nc + q // 2), rm * (nc + 1), nc * r
         if aff:  # per line job: one tau for the parent centre, per child one tau and 1 + q/2 pairs
             return rm * nc * half, rm * (nc + 1), nc * r
         return nc * r, nc * r + r, nc * r
