@@ -204,6 +204,85 @@ def traffic_per_launch(kernel_family: str, prec: str):
     return None if fam is None else fam.get("hbm_bytes_per_launch")
 
 
+TRAFFIC_BENCH = ("python3 bench.py --steps 2 --warmup 1 --no-tune --no-cpu-baseline --no-c5 --no-c4 --no-3d "
+                 "--no-sparse --no-c1 --no-adjoint --no-rhs")
+
+
+def summarize_traffic(d: str) -> int:
+    """Write profiles/c2_hbm_traffic.json from four rocprofv3 counter runs
+    under d: fetch/ and write/ (FETCH_SIZE, WRITE_SIZE of the C2 bench legs,
+    TRAFFIC_BENCH) and copy_fetch/, copy_write/ (the same counters of
+    --copy-calibration).  The counters are KiB per dispatch; each is scaled
+    by what it reads for the plain 1 GiB copy, and the level kernels' values
+    are averaged per kernel family and precision."""
+    import csv
+    import glob
+    import hashlib
+    import re
+
+    def rows(sub):
+        paths = glob.glob(os.path.join(d, sub, "**", "*counter_collection.csv"), recursive=True)
+        if len(paths) != 1:
+            raise SystemExit(f"expected one counter_collection.csv under {os.path.join(d, sub)}, found {len(paths)}")
+        with open(paths[0]) as fh:
+            return list(csv.DictReader(fh))
+
+    def per_dispatch(sub, counter):
+        out = {}
+        for r in rows(sub):
+            if r["Counter_Name"] == counter:
+                out.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        return out
+
+    def copy_kib(sub, counter):
+        vals = [v for name, v in per_dispatch(sub, counter).values() if "copy" in name.lower()]
+        if not vals:
+            raise SystemExit(f"no copy kernel in {sub}")
+        return max(vals)
+
+    copy_bytes = 1 << 30
+    fk, wk = copy_kib("copy_fetch", "FETCH_SIZE"), copy_kib("copy_write", "WRITE_SIZE")
+    ff, wf = copy_bytes / (fk * 1024.0), copy_bytes / (wk * 1024.0)
+    fetch, write = per_dispatch("fetch", "FETCH_SIZE"), per_dispatch("write", "WRITE_SIZE")
+    fams = {}
+    for table, key in ((fetch, "fetch"), (write, "write")):
+        for name, v in table.values():
+            m = re.search(r"\b(k_first|k_second|k_final)<\d+, \d+, (float|double),", name)
+            if m:
+                fam = f"{m.group(1)} {'fp64' if m.group(2) == 'double' else 'fp32'}"
+                fams.setdefault(fam, {"fetch": [], "write": []})[key].append(v)
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    kernels = {}
+    for fam, v in sorted(fams.items()):
+        f, w_ = float(np.mean(v["fetch"])), float(np.mean(v["write"]))
+        kernels[fam] = {"fetch_kib_raw_per_launch": round(f, 1), "write_kib_raw_per_launch": round(w_, 1),
+                        "hbm_bytes_per_launch": int(round((f * ff + w_ * wf) * 1024)),
+                        "launches_sampled": min(len(v["fetch"]), len(v["write"]))}
+    rec = {"what": "HBM bytes per launch of the level kernels on the C2 workload (2-D hyperbolic Radon, N=1024, "
+                   "q=5, 1 RHS, built-in launch shapes), from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per "
+                   f"dispatch) scaled by a 1 GiB plain device copy: fetch factor {ff:.4f}, write factor {wf:.4f}.",
+           "commands": ["cd /tmp && export TMPDIR=/tmp",
+                        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <d>/fetch -o c2 -- {TRAFFIC_BENCH}",
+                        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <d>/write -o c2 -- {TRAFFIC_BENCH}",
+                        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <d>/copy_fetch -o copy -- "
+                        "python3 bench.py --copy-calibration",
+                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <d>/copy_write -o copy -- "
+                        "python3 bench.py --copy-calibration",
+                        "python3 bench.py --summarize-traffic <d>"],
+           "copy_calibration": {"bytes_copied": copy_bytes, "fetch_kib_raw": fk, "write_kib_raw": wk,
+                                "fetch_factor": ff, "write_factor": wf},
+           "source_sha256": h.hexdigest(), "kernels": kernels}
+    path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(kernels, indent=1))
+    return 0
+
+
 def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
@@ -491,7 +570,11 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true", help="time the built-in launch shapes only (no autotuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one plain device copy of 1 GiB (scales the HBM byte counters)")
+    ap.add_argument("--summarize-traffic", metavar="DIR",
+                    help="only write profiles/c2_hbm_traffic.json from the rocprofv3 counter runs under DIR")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        return summarize_traffic(args.summarize_traffic)
     if args.copy_calibration:
         import torch
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
