@@ -85,11 +85,12 @@ enum {
  *  FP32     phase tau and its reduction modulo 1 in FP64, then FP32
  *           sine/cosine, FP32 weights and FP32 contractions.
  *  SPLIT32  hi/lo pairs of FP32 values with error-free accumulation: NOT
- *           built.  Every entry point that takes a precision returns
- *           BFLY_EUNSUPPORTED for it.  On gfx950 the FP64 vector unit issues
- *           at the non-packed FP32 rate, and a double-float multiply-add
- *           takes 18 FP32 instructions (measured 7.3x slower than an FP64
- *           multiply-add), so the FP64 mode gives near-FP64 results faster. */
+ *           implemented.  Every entry point that takes a precision returns
+ *           BFLY_EUNSUPPORTED for it.  On gfx950 an FP64 multiply-add costs
+ *           about twice an FP32 one (measured 58.7 against 112 TFLOP/s),
+ *           while a double-float multiply-add takes 18 FP32 instructions
+ *           (measured 7.3x slower than an FP64 multiply-add), so the FP64
+ *           mode gives near-FP64 results faster. */
 enum { BFLY_FP64 = 0, BFLY_FP32 = 1, BFLY_SPLIT32 = 2 };
 
 /* Create a plan.
