@@ -184,21 +184,29 @@ def measure_contraction_units(torch, P, dev) -> dict:
     return res
 
 
+def kernel_sources_sha256() -> str:
+    """Hash of the device-code sources (.hip, .inc, .h under csrc/): the
+    counter summary is valid while they are unchanged (host-only .cpp files
+    do not affect the kernels' traffic)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".inc", ".h")):
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(name.encode() + fh.read())
+    return h.hexdigest()
+
+
 def traffic_per_launch(kernel_family: str, prec: str):
     """HBM bytes per launch of a kernel family in one precision from the
     committed counter summary, or None if the kernel sources changed since it
     was taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        with open(os.path.join(CSRC, name), "rb") as fh:
-            h.update(name.encode() + fh.read())
-    if rec.get("source_sha256") != h.hexdigest():
+    if rec.get("source_sha256") != kernel_sources_sha256():
         return None
     fam = rec.get("kernels", {}).get(f"{kernel_family} {prec}")
     return None if fam is None else fam.get("hbm_bytes_per_launch")
@@ -217,7 +225,6 @@ def summarize_traffic(d: str) -> int:
     are averaged per kernel family and precision."""
     import csv
     import glob
-    import hashlib
     import re
 
     def rows(sub):
@@ -251,10 +258,6 @@ def summarize_traffic(d: str) -> int:
             if m:
                 fam = f"{m.group(1)} {'fp64' if m.group(2) == 'double' else 'fp32'}"
                 fams.setdefault(fam, {"fetch": [], "write": []})[key].append(v)
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        with open(os.path.join(CSRC, name), "rb") as fh:
-            h.update(name.encode() + fh.read())
     kernels = {}
     for fam, v in sorted(fams.items()):
         f, w_ = float(np.mean(v["fetch"])), float(np.mean(v["write"]))
@@ -274,7 +277,7 @@ def summarize_traffic(d: str) -> int:
                         "python3 bench.py --summarize-traffic <d>"],
            "copy_calibration": {"bytes_copied": copy_bytes, "fetch_kib_raw": fk, "write_kib_raw": wk,
                                 "fetch_factor": ff, "write_factor": wf},
-           "source_sha256": h.hexdigest(), "kernels": kernels}
+           "source_sha256": kernel_sources_sha256(), "kernels": kernels}
     path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.json")
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
