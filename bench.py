@@ -33,6 +33,7 @@ CSRC = os.path.join(ROOT, "paper_1305_4650_amd", "csrc")
 # in FP64; its roofline is taken against the FP32 peak, an FP64 operation counting as two FP32 ones
 # (half the rate).  (The contraction-rate microkernel measures non-packed v_fma_f32 at about 73% of
 # 157.3 on this part, the same fraction FP64 FMAs reach of 78.6, so 78.6 would not bound FP32.)
+HBM_PEAK_TBPS = 8.0  # MI355X HBM3E, published
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # Flops charged per evaluation of tau: the operations of its definition, a
 # square root counted as one operation (the kernels' correctly rounded FP64
@@ -706,8 +707,14 @@ def main() -> int:
                         "frac": round(fl / (rec["ms"] * 1e-3) / 1e12 / PEAK_TFLOPS[prec], 4) if fl else None})
         total_flops = sum(kind_flops(k, tim[k], fm) for k in tim)
         total_s = sum(t["ms"] for t in tim.values()) * 1e-3
+        traffic = traffic_per_launch(fam, prec)
+        # the other roofline of the same launches: measured HBM bytes per
+        # launch over their duration, against the 8 TB/s peak
+        hbm = None if traffic is None else traffic / (avg_ms * 1e-3) / 1e12
         return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": traffic_per_launch(fam, prec),
+                "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": traffic,
+                "hbm_tb_per_s": None if hbm is None else round(hbm, 3),
+                "hbm_frac": None if hbm is None else round(hbm / HBM_PEAK_TBPS, 4),
                 "kernel": fam, "avg_launch_ms": round(avg_ms, 5), "algorithmic_flops_per_launch": round(flops),
                 "c_cs_flops": phase_cost[prec]["c_cs_flops"], "launches_of_one_apply": per,
                 "apply": {"achieved": round(total_flops / total_s / 1e12, 3),
