@@ -67,6 +67,12 @@ def lib():
                                     ctypes.c_long, dp, dp, ctypes.c_long,
                                     ctypes.c_long, dp, dp, ctypes.c_long,
                                     ctypes.c_int, ctypes.c_int, dp]
+        L.orc_butterfly_dump.restype = ctypes.c_int
+        L.orc_butterfly_dump.argtypes = [ctypes.c_int, ctypes.c_long, ctypes.c_int, ctypes.c_int,
+                                         dp, dp, dp, dp, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_long, dp, dp, ctypes.c_long,
+                                         ctypes.c_long, dp, dp, ctypes.c_long,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -163,3 +169,36 @@ def butterfly(phase, N: int, q: int, src_box, tgt_box, pts_in, vals, pts_out,
     if return_counts:
         return out, {"phase": counts[0], "mac": counts[1], "cmac": counts[2], "stages": counts[3]}
     return out
+
+
+def butterfly_weights(phase, N: int, q: int, src_box, tgt_box, pts_in, vals, step: int,
+                      adjoint: bool = False, switch_level: int = -1, nthreads: int = 0):
+    """The butterfly's weights after one step (orc_butterfly_dump, a test and
+    debugging hook): step 0 after the initialisation, k in 1..ls after
+    column-space stage k-1, ls+1 after the middle switch, k in ls+2..L+1
+    after row-space stage k-2.  Returns complex (N^d pairs, q^d nodes, nrhs)
+    indexed [(a << d (L - lvl)) | b][t][rhs] with a, b the target and source
+    box indices of the level (dimension j at bits lvl * j, resp. (L - lvl) * j)."""
+    slo = np.ascontiguousarray(src_box[0], dtype=np.float64)
+    shi = np.ascontiguousarray(src_box[1], dtype=np.float64)
+    tlo = np.ascontiguousarray(tgt_box[0], dtype=np.float64)
+    thi = np.ascontiguousarray(tgt_box[1], dtype=np.float64)
+    d = slo.size
+    L = int(N).bit_length() - 1
+    if not 0 <= step <= L + 1:
+        raise ValueError(f"step {step} outside 0..{L + 1}")
+    pin = _pts(pts_in, d)
+    vi = _cplx(vals, pin.shape[0])
+    nrhs = vi.shape[0]
+    P, r = N ** d, q ** d
+    dump = np.zeros((P, r, nrhs), dtype=np.complex128)
+    pout = np.zeros((0, d))
+    out = np.zeros((nrhs, 0), dtype=np.complex128)
+    rc = lib().orc_butterfly_dump(d, N, q, _phase_id(phase), _dp(slo), _dp(shi), _dp(tlo), _dp(thi),
+                                  int(adjoint), switch_level,
+                                  pin.shape[0], _dp(pin), _dp(vi.view(np.float64)), pin.shape[0],
+                                  0, _dp(pout), _dp(out.view(np.float64)), 1,
+                                  nrhs, nthreads, int(step), _dp(dump.view(np.float64)))
+    if rc:
+        raise ValueError(f"orc_butterfly_dump rejected its arguments (rc={rc})")
+    return dump

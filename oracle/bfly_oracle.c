@@ -317,13 +317,15 @@ int orc_direct(int phase, int d, long N, int adjoint,
 /* Butterfly apply (Alg. "alg:serial")                                      */
 /* ------------------------------------------------------------------------ */
 
-int orc_butterfly(int d, long N, int q, int phase,
-                  const double* slo, const double* shi,
-                  const double* tlo, const double* thi,
-                  int adjoint, int switch_level,
-                  long n_in, const double* pts_in, const double* in, long ldin,
-                  long n_out, const double* pts_out, double* out, long ldout,
-                  int nrhs, int nthreads, double* counts) {
+/* The apply; when dump is not NULL, the weights after step dump_at are
+ * copied there (see orc_butterfly_dump). */
+static int butterfly(int d, long N, int q, int phase,
+                     const double* slo, const double* shi,
+                     const double* tlo, const double* thi,
+                     int adjoint, int switch_level,
+                     long n_in, const double* pts_in, const double* in, long ldin,
+                     long n_out, const double* pts_out, double* out, long ldout,
+                     int nrhs, int nthreads, double* counts, int dump_at, double* dump) {
   prob pb;
   if (setup(&pb, d, N, q, phase, slo, shi, tlo, thi, adjoint, switch_level, nrhs)) return 1;
   const prob* p = &pb;
@@ -342,6 +344,12 @@ int orc_butterfly(int d, long N, int q, int phase,
     free(tab);
     return 2;
   }
+
+  /* the weights after a step, for orc_butterfly_dump */
+#define ORC_DUMP(step)                                                      \
+  do {                                                                      \
+    if (dump && dump_at == (step)) memcpy(dump, W, sizeof(cplx) * (size_t)P * vec); \
+  } while (0)
 
   /* ---- 1. bin the sources into the N^d leaves of the source tree (stable) */
   long* leaf = (long*)malloc(sizeof(long) * (size_t)(n_in > 0 ? n_in : 1));
@@ -404,6 +412,8 @@ int orc_butterfly(int d, long N, int q, int phase,
     }
   }
 
+  ORC_DUMP(0);
+
   /* ---- 3. first half: stages l = 0 .. ls-1, column-space interpolation.
    * Group = (parent target box P at level l, merged source box B' at level
    * l+1); each child target box A' of P gets
@@ -457,6 +467,7 @@ int orc_butterfly(int d, long N, int q, int phase,
     cplx* tmp = W;
     W = Wn;
     Wn = tmp;
+    ORC_DUMP(l + 1);
   }
 
   /* ---- 4. middle switch at level ls (Sec. 1.4): equivalent sources at the
@@ -494,6 +505,7 @@ int orc_butterfly(int d, long N, int q, int phase,
     cplx* tmp = W;
     W = Wn;
     Wn = tmp;
+    ORC_DUMP(p->ls + 1);
   }
 
   /* ---- 5. second half: stages l = ls .. L-1, row-space interpolation
@@ -564,7 +576,9 @@ int orc_butterfly(int d, long N, int q, int phase,
     cplx* tmp = W;
     W = Wn;
     Wn = tmp;
+    ORC_DUMP(l + 2);
   }
+#undef ORC_DUMP
 
   /* ---- 6. final evaluation f_AY := U_AY w_AY (Sec. 1; Alg. "alg:serial"):
    * f(x) = e^{i Phi(x, c_Y)} sum_t L^A_t(x) e^{-i Phi(x^A_t, c_Y)} delta^{AY}_t. */
@@ -626,4 +640,26 @@ int orc_butterfly(int d, long N, int q, int phase,
   free(start);
   free(order);
   return 0;
+}
+
+int orc_butterfly(int d, long N, int q, int phase,
+                  const double* slo, const double* shi,
+                  const double* tlo, const double* thi,
+                  int adjoint, int switch_level,
+                  long n_in, const double* pts_in, const double* in, long ldin,
+                  long n_out, const double* pts_out, double* out, long ldout,
+                  int nrhs, int nthreads, double* counts) {
+  return butterfly(d, N, q, phase, slo, shi, tlo, thi, adjoint, switch_level, n_in, pts_in, in, ldin, n_out,
+                   pts_out, out, ldout, nrhs, nthreads, counts, -1, NULL);
+}
+
+int orc_butterfly_dump(int d, long N, int q, int phase,
+                       const double* slo, const double* shi,
+                       const double* tlo, const double* thi,
+                       int adjoint, int switch_level,
+                       long n_in, const double* pts_in, const double* in, long ldin,
+                       long n_out, const double* pts_out, double* out, long ldout,
+                       int nrhs, int nthreads, int dump_at, double* dump) {
+  return butterfly(d, N, q, phase, slo, shi, tlo, thi, adjoint, switch_level, n_in, pts_in, in, ldin, n_out,
+                   pts_out, out, ldout, nrhs, nthreads, NULL, dump_at, dump);
 }

@@ -63,6 +63,27 @@ int orc_butterfly(int d, long N, int q, int phase,
                   long n_out, const double* pts_out, double* out, long ldout,
                   int nrhs, int nthreads, double* counts);
 
+/* orc_butterfly, with the weights after one step copied to dump (a debugging
+ * and test hook, so that a stage of another implementation can be compared
+ * with this one's): dump_at = 0 after the initialisation (level 0), k in
+ * 1..ls after column-space stage k-1 (level k), ls+1 after the middle switch
+ * (level ls), k in ls+2..L+1 after row-space stage k-2 (level k-1), before
+ * the final evaluation.  dump holds P * r * nrhs complex values (P = N^d):
+ * [pair][t][rhs], pair = (a << d (L - lvl)) | b for the target box index a
+ * (lvl bits per dimension, dimension j at bits lvl*j) and the source box
+ * index b (L - lvl bits per dimension, likewise); t = sum_j t_j q^j.  The
+ * weights are the equivalent sources of Sec. 1.2 up to the switch and the
+ * potentials at the target nodes after it.  A step outside 0..L+1 leaves
+ * dump untouched; the other arguments and the return codes are
+ * orc_butterfly's. */
+int orc_butterfly_dump(int d, long N, int q, int phase,
+                       const double* slo, const double* shi,
+                       const double* tlo, const double* thi,
+                       int adjoint, int switch_level,
+                       long n_in, const double* pts_in, const double* in, long ldin,
+                       long n_out, const double* pts_out, double* out, long ldout,
+                       int nrhs, int nthreads, int dump_at, double* dump);
+
 #ifdef __cplusplus
 }
 #endif
