@@ -1,0 +1,103 @@
+"""Stage-level parity: the library's last-level weights against the oracle's.
+
+After an apply the weight buffer at the start of the workspace holds the
+weights of the last level, before the final evaluation: for target leaf A
+and node t, e^{-i Phi(x^A_t, c_Y)} delta^{AY}_t (the row-space form,
+demodulated by the root source box's centre c_Y), in slot order ([slot][node],
+one right-hand side; the slot interleaves the bits of A's index, coarsest
+split first).  The oracle returns delta^{AY}_t after its last stage
+(orc_butterfly_dump, step L + 1).  The two are compared vector by vector,
+with the same FP64 / FP32 bars as the outputs: a mistake that the final
+evaluation's interpolation smooths over would still show here.
+"""
+import numpy as np
+import pytest
+
+from paper_1305_4650_amd import workloads as W
+from parity_norms import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def tau_hypradon2(N, x0, x1, y0, y1):
+    """The hyperbolic-Radon phase in turns, in the oracle's operation order
+    (checked bit for bit against the oracle's own below)."""
+    a = y0 * y0
+    b = x1 * x1
+    c = y1 * y1
+    e = b * c
+    s = a + e
+    m = float(N) * x0
+    return m * np.sqrt(s)
+
+
+def leaf_nodes(w, L, z):
+    """Target leaf nodes x^A_t, indexed [a0 + N a1][t0 + q t1], with the
+    library's box arithmetic (centre + half width times node)."""
+    N, q = w.N, w.q
+    tlo, thi = w.tgt_box
+    wd = (np.asarray(thi) - np.asarray(tlo)) / N
+    a = np.arange(N)
+    c0 = tlo[0] + (a + 0.5) * wd[0]
+    c1 = tlo[1] + (a + 0.5) * wd[1]
+    h0, h1 = 0.5 * wd[0], 0.5 * wd[1]
+    x0 = c0[:, None] + h0 * z[None, :]          # [a0][t0]
+    x1 = c1[:, None] + h1 * z[None, :]          # [a1][t1]
+    X0 = np.broadcast_to(x0[None, :, None, :], (N, N, q, q))  # [a1][a0][t1][t0]
+    X1 = np.broadcast_to(x1[:, None, :, None], (N, N, q, q))
+    return X0.reshape(N * N, q * q), X1.reshape(N * N, q * q)
+
+
+def slots(N, L):
+    """Slot of target leaf A = (a0, a1) at the last level, for A's oracle
+    index a0 + N a1: bit k of the slot's digit d is bit L-1-k of a_d."""
+    a = np.arange(N * N)
+    a0, a1 = a % N, a // N
+    s = np.zeros(N * N, dtype=np.int64)
+    for k in range(L):
+        s |= ((a0 >> (L - 1 - k)) & 1) << (2 * k)
+        s |= ((a1 >> (L - 1 - k)) & 1) << (2 * k + 1)
+    return s
+
+
+CASES = [
+    ("hypradon2_N128_q5", lambda: W.hypradon2(128, q=5), "fp64", 1e-12),
+    ("hypradon2_N128_q5", lambda: W.hypradon2(128, q=5), "fp32", 1e-5),
+    ("C2_hypradon2_N1024_q5", lambda: W.C2(), "fp64", 1e-12),
+    ("C2_hypradon2_N1024_q5", lambda: W.C2(), "fp32", 1e-5),
+]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name, make, prec, tol", CASES, ids=[f"{c[0]}-{c[2]}" for c in CASES])
+def test_last_level_weights_match_oracle(orc, name, make, prec, tol):
+    import torch
+    import paper_1305_4650_amd as P
+    w = make()
+    N, q = w.N, w.q
+    L = N.bit_length() - 1
+    r = q * q
+    print(f"[case] last-level weights {name} {prec}", flush=True)
+    plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+    y, x, g = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (w.y, w.x, w.g))
+    ws = plan.workspace(w.y.shape[0], 1, prec)
+    plan.apply(y, g, x, prec, workspace=ws)
+    torch.cuda.synchronize()
+    dt = np.complex128 if prec == "fp64" else np.complex64
+    nbytes = N * N * r * np.dtype(dt).itemsize
+    got = ws[:nbytes].cpu().numpy().view(dt).reshape(N * N, r).astype(np.complex128)
+    del ws
+
+    delta = orc.butterfly_weights(w.phase, N, q, w.src_box, w.tgt_box, w.y, w.g, L + 1)[:, :, 0]
+    z = orc.nodes(q)
+    X0, X1 = leaf_nodes(w, L, z)
+    slo, shi = (np.asarray(b, dtype=np.float64) for b in w.src_box)
+    cy = slo + 0.5 * (shi - slo)  # the root source box's centre, as the library forms it
+    t = tau_hypradon2(N, X0, X1, cy[0], cy[1])
+    # the phase as written here is the oracle's, bit for bit
+    rng = np.random.default_rng(5)
+    for i in rng.choice(t.size, 200, replace=False):
+        a, k = divmod(int(i), r)
+        assert t[a, k] == orc.tau(w.phase, N, [X0[a, k], X1[a, k]], cy)
+    want = delta * np.exp(-2j * np.pi * (t - np.rint(t)))
+    assert_parity(got[slots(N, L)], want, tol, what=f"{name} {prec} last-level weights")
