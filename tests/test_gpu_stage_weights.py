@@ -31,11 +31,12 @@ def tau_hypradon2(N, x0, x1, y0, y1):
     return m * np.sqrt(s)
 
 
-def leaf_nodes(w, L, z):
-    """Target leaf nodes x^A_t, indexed [a0 + N a1][t0 + q t1], with the
-    library's box arithmetic (centre + half width times node)."""
+def leaf_nodes(w, L, z, box=None):
+    """Target-role leaf nodes x^A_t, indexed [a0 + N a1][t0 + q t1], with the
+    library's box arithmetic (centre + half width times node); the target
+    role is the plan's target box, or the given box (the adjoint's)."""
     N, q = w.N, w.q
-    tlo, thi = w.tgt_box
+    tlo, thi = w.tgt_box if box is None else box
     wd = (np.asarray(thi) - np.asarray(tlo)) / N
     a = np.arange(N)
     c0 = tlo[0] + (a + 0.5) * wd[0]
@@ -101,3 +102,49 @@ def test_last_level_weights_match_oracle(orc, name, make, prec, tol):
         assert t[a, k] == orc.tau(w.phase, N, [X0[a, k], X1[a, k]], cy)
     want = delta * np.exp(-2j * np.pi * (t - np.rint(t)))
     assert_parity(got[slots(N, L)], want, tol, what=f"{name} {prec} last-level weights")
+
+
+ADJ_CASES = [
+    ("hypradon2_N128_q5", lambda: W.hypradon2(128, q=5), "fp64", 1e-12),
+    ("C2_hypradon2_N1024_q5", lambda: W.C2(), "fp64", 1e-12),
+    ("C2_hypradon2_N1024_q5", lambda: W.C2(), "fp32", 1e-5),
+]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name, make, prec, tol", ADJ_CASES, ids=[f"{c[0]}-{c[2]}" for c in ADJ_CASES])
+def test_adjoint_last_level_weights_match_oracle(orc, name, make, prec, tol):
+    """The adjoint apply (roles swapped, phase -Phi(x, y), mirror switch
+    level): its last level lives on the leaves of the plan's source box, and
+    is demodulated by the plan's target-box centre c_X, i.e. multiplied by
+    e^{+i Phi(c_X, y_t)}."""
+    import torch
+    import paper_1305_4650_amd as P
+    w = make()
+    N, q = w.N, w.q
+    L = N.bit_length() - 1
+    r = q * q
+    rng = np.random.default_rng(17)
+    f = rng.standard_normal((1, w.x.shape[0])) + 1j * rng.standard_normal((1, w.x.shape[0]))
+    print(f"[case] adjoint last-level weights {name} {prec}", flush=True)
+    plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+    y, x, fd = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (w.y, w.x, f))
+    ws = plan.workspace(w.x.shape[0], 1, prec)
+    plan.apply_adjoint(x, fd, y, prec, workspace=ws)
+    torch.cuda.synchronize()
+    dt = np.complex128 if prec == "fp64" else np.complex64
+    nbytes = N * N * r * np.dtype(dt).itemsize
+    got = ws[:nbytes].cpu().numpy().view(dt).reshape(N * N, r).astype(np.complex128)
+    del ws
+
+    delta = orc.butterfly_weights(w.phase, N, q, w.src_box, w.tgt_box, w.x, f, L + 1, adjoint=True)[:, :, 0]
+    z = orc.nodes(q)
+    Y0, Y1 = leaf_nodes(w, L, z, box=w.src_box)
+    tlo, thi = (np.asarray(b, dtype=np.float64) for b in w.tgt_box)
+    cx = tlo + 0.5 * (thi - tlo)
+    t = tau_hypradon2(N, cx[0], cx[1], Y0, Y1)
+    for i in rng.choice(t.size, 200, replace=False):
+        a, k = divmod(int(i), r)
+        assert t[a, k] == orc.tau(w.phase, N, cx, [Y0[a, k], Y1[a, k]])
+    want = delta * np.exp(2j * np.pi * (t - np.rint(t)))
+    assert_parity(got[slots(N, L)], want, tol, what=f"{name} {prec} adjoint last-level weights")
