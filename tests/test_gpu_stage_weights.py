@@ -31,6 +31,15 @@ def tau_hypradon2(N, x0, x1, y0, y1):
     return m * np.sqrt(s)
 
 
+def tau_fourier(N, x0, x1, y0, y1):
+    """x . y in turns, in the oracle's operation order."""
+    s = x0 * y0
+    return s + x1 * y1
+
+
+TAU = {"hypradon2": tau_hypradon2, "fourier": tau_fourier}
+
+
 def leaf_nodes(w, L, z, box=None):
     """Target-role leaf nodes x^A_t, indexed [a0 + N a1][t0 + q t1], with the
     library's box arithmetic (centre + half width times node); the target
@@ -62,6 +71,8 @@ def slots(N, L):
 
 
 CASES = [
+    ("C1_fourier2d_N64_q5", lambda: W.C1(), "fp64", 1e-12),
+    ("C1_fourier2d_N64_q5", lambda: W.C1(), "fp32", 1e-5),
     ("hypradon2_N128_q5", lambda: W.hypradon2(128, q=5), "fp64", 1e-12),
     ("hypradon2_N128_q5", lambda: W.hypradon2(128, q=5), "fp32", 1e-5),
     ("C2_hypradon2_N1024_q5", lambda: W.C2(), "fp64", 1e-12),
@@ -94,7 +105,7 @@ def test_last_level_weights_match_oracle(orc, name, make, prec, tol):
     X0, X1 = leaf_nodes(w, L, z)
     slo, shi = (np.asarray(b, dtype=np.float64) for b in w.src_box)
     cy = slo + 0.5 * (shi - slo)  # the root source box's centre, as the library forms it
-    t = tau_hypradon2(N, X0, X1, cy[0], cy[1])
+    t = TAU[w.phase](N, X0, X1, cy[0], cy[1])
     # the phase as written here is the oracle's, bit for bit
     rng = np.random.default_rng(5)
     for i in rng.choice(t.size, 200, replace=False):
@@ -105,6 +116,7 @@ def test_last_level_weights_match_oracle(orc, name, make, prec, tol):
 
 
 ADJ_CASES = [
+    ("C1_fourier2d_N64_q5", lambda: W.C1(), "fp64", 1e-12),
     ("hypradon2_N128_q5", lambda: W.hypradon2(128, q=5), "fp64", 1e-12),
     ("C2_hypradon2_N1024_q5", lambda: W.C2(), "fp64", 1e-12),
     ("C2_hypradon2_N1024_q5", lambda: W.C2(), "fp32", 1e-5),
@@ -142,7 +154,7 @@ def test_adjoint_last_level_weights_match_oracle(orc, name, make, prec, tol):
     Y0, Y1 = leaf_nodes(w, L, z, box=w.src_box)
     tlo, thi = (np.asarray(b, dtype=np.float64) for b in w.tgt_box)
     cx = tlo + 0.5 * (thi - tlo)
-    t = tau_hypradon2(N, cx[0], cx[1], Y0, Y1)
+    t = TAU[w.phase](N, cx[0], cx[1], Y0, Y1)
     for i in rng.choice(t.size, 200, replace=False):
         a, k = divmod(int(i), r)
         assert t[a, k] == orc.tau(w.phase, N, cx, [Y0[a, k], Y1[a, k]])
