@@ -160,3 +160,77 @@ def test_adjoint_last_level_weights_match_oracle(orc, name, make, prec, tol):
         assert t[a, k] == orc.tau(w.phase, N, cx, [Y0[a, k], Y1[a, k]])
     want = delta * np.exp(2j * np.pi * (t - np.rint(t)))
     assert_parity(got[slots(N, L)], want, tol, what=f"{name} {prec} adjoint last-level weights")
+
+
+def leaf_nodes_nd(box, N, q, d, z):
+    """Leaf nodes of a box in d dimensions, [a_lin][t][j] with a_lin =
+    sum_j a_j N^j and t = sum_j t_j q^j (the library's box arithmetic)."""
+    lo, hi = (np.asarray(b, dtype=np.float64) for b in box)
+    wd = (hi - lo) / N
+    out = np.empty((N ** d, q ** d, d))
+    for j in range(d):
+        a_j = (np.arange(N ** d) // N ** j) % N
+        t_j = (np.arange(q ** d) // q ** j) % q
+        c = lo[j] + (a_j + 0.5) * wd[j]
+        out[:, :, j] = c[:, None] + (0.5 * wd[j]) * z[t_j][None, :]
+    return out
+
+
+def slots_nd(N, L, d):
+    a = np.arange(N ** d)
+    s = np.zeros(N ** d, dtype=np.int64)
+    for j in range(d):
+        a_j = (a // N ** j) % N
+        for k in range(L):
+            s |= ((a_j >> (L - 1 - k)) & 1) << (d * k + j)
+    return s
+
+
+CASES_3D = [("genradon3_N16_q4", "fp64", 1e-12, False), ("genradon3_N16_q4", "fp32", 1e-5, False),
+            ("genradon3_N16_q4", "fp64", 1e-12, True)]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name, prec, tol, adjoint", CASES_3D,
+                         ids=[f"{c[0]}-{c[1]}-{'adj' if c[3] else 'fwd'}" for c in CASES_3D])
+def test_3d_last_level_weights_match_oracle(orc, name, prec, tol, adjoint):
+    """The generalized-Radon phase in 3-D (the phase's sine and cosine terms
+    make the demodulation factors come from the oracle's own phase, node by
+    node)."""
+    import torch
+    import paper_1305_4650_amd as P
+    w = W.genradon3(16, q=4)
+    N, q, d = w.N, w.q, w.d
+    L = N.bit_length() - 1
+    r = q ** d
+    rng = np.random.default_rng(23)
+    print(f"[case] 3-D last-level weights {name} {prec} {'adjoint' if adjoint else 'forward'}", flush=True)
+    plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+    y, x = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (w.y, w.x))
+    if adjoint:
+        f = rng.standard_normal((1, w.x.shape[0])) + 1j * rng.standard_normal((1, w.x.shape[0]))
+        ws = plan.workspace(w.x.shape[0], 1, prec)
+        plan.apply_adjoint(x, torch.from_numpy(f).cuda(), y, prec, workspace=ws)
+    else:
+        ws = plan.workspace(w.y.shape[0], 1, prec)
+        plan.apply(y, torch.from_numpy(np.ascontiguousarray(w.g)).cuda(), x, prec, workspace=ws)
+    torch.cuda.synchronize()
+    dt = np.complex128 if prec == "fp64" else np.complex64
+    got = ws[:N ** d * r * np.dtype(dt).itemsize].cpu().numpy().view(dt).reshape(N ** d, r).astype(np.complex128)
+    del ws
+    z = orc.nodes(q)
+    if adjoint:
+        delta = orc.butterfly_weights(w.phase, N, q, w.src_box, w.tgt_box, w.x, f, L + 1, adjoint=True)[:, :, 0]
+        nodes = leaf_nodes_nd(w.src_box, N, q, d, z)
+        lo, hi = (np.asarray(b, dtype=np.float64) for b in w.tgt_box)
+        c = lo + 0.5 * (hi - lo)
+        t = np.array([[orc.tau(w.phase, N, c, nodes[a, k]) for k in range(r)] for a in range(N ** d)])
+        want = delta * np.exp(2j * np.pi * (t - np.rint(t)))
+    else:
+        delta = orc.butterfly_weights(w.phase, N, q, w.src_box, w.tgt_box, w.y, w.g, L + 1)[:, :, 0]
+        nodes = leaf_nodes_nd(w.tgt_box, N, q, d, z)
+        lo, hi = (np.asarray(b, dtype=np.float64) for b in w.src_box)
+        c = lo + 0.5 * (hi - lo)
+        t = np.array([[orc.tau(w.phase, N, nodes[a, k], c) for k in range(r)] for a in range(N ** d)])
+        want = delta * np.exp(-2j * np.pi * (t - np.rint(t)))
+    assert_parity(got[slots_nd(N, L, d)], want, tol, what=f"{name} {prec} last-level weights")
