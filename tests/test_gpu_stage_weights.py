@@ -186,25 +186,32 @@ def slots_nd(N, L, d):
     return s
 
 
-CASES_3D = [("genradon3_N16_q4", "fp64", 1e-12, False), ("genradon3_N16_q4", "fp32", 1e-5, False),
-            ("genradon3_N16_q4", "fp64", 1e-12, True)]
+CASES_ND = [
+    ("genradon3_N16_q4", lambda: W.genradon3(16, q=4), "fp64", 1e-12, False),
+    ("genradon3_N16_q4", lambda: W.genradon3(16, q=4), "fp32", 1e-5, False),
+    ("genradon3_N16_q4", lambda: W.genradon3(16, q=4), "fp64", 1e-12, True),
+    ("fourier1d_N64_q8", lambda: W.fourier_grid(64, d=1, q=8), "fp64", 1e-12, False),
+    ("fourier1d_N64_q8", lambda: W.fourier_grid(64, d=1, q=8), "fp32", 1e-5, False),
+    ("fourier1d_N64_q8", lambda: W.fourier_grid(64, d=1, q=8), "fp64", 1e-12, True),
+]
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("name, prec, tol, adjoint", CASES_3D,
-                         ids=[f"{c[0]}-{c[1]}-{'adj' if c[3] else 'fwd'}" for c in CASES_3D])
-def test_3d_last_level_weights_match_oracle(orc, name, prec, tol, adjoint):
-    """The generalized-Radon phase in 3-D (the phase's sine and cosine terms
-    make the demodulation factors come from the oracle's own phase, node by
-    node)."""
+@pytest.mark.parametrize("name, make, prec, tol, adjoint", CASES_ND,
+                         ids=[f"{c[0]}-{c[2]}-{'adj' if c[4] else 'fwd'}" for c in CASES_ND])
+def test_nd_last_level_weights_match_oracle(orc, name, make, prec, tol, adjoint):
+    """Other dimensions: the 3-D generalized-Radon phase (its sine and
+    cosine terms make the demodulation factors come from the oracle's own
+    phase, node by node) and the 1-D Fourier phase (slot = bit-reversed leaf
+    index)."""
     import torch
     import paper_1305_4650_amd as P
-    w = W.genradon3(16, q=4)
+    w = make()
     N, q, d = w.N, w.q, w.d
     L = N.bit_length() - 1
     r = q ** d
     rng = np.random.default_rng(23)
-    print(f"[case] 3-D last-level weights {name} {prec} {'adjoint' if adjoint else 'forward'}", flush=True)
+    print(f"[case] last-level weights {name} {prec} {'adjoint' if adjoint else 'forward'}", flush=True)
     plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
     y, x = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (w.y, w.x))
     if adjoint:
