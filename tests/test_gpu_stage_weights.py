@@ -241,3 +241,35 @@ def test_nd_last_level_weights_match_oracle(orc, name, make, prec, tol, adjoint)
         t = np.array([[orc.tau(w.phase, N, nodes[a, k], c) for k in range(r)] for a in range(N ** d)])
         want = delta * np.exp(-2j * np.pi * (t - np.rint(t)))
     assert_parity(got[slots_nd(N, L, d)], want, tol, what=f"{name} {prec} last-level weights")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec, tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_chunked_rhs_last_level_weights_match_oracle(orc, prec, tol):
+    """Three right-hand sides: a chunk of two ([slot][node][2]) and one more
+    chunk of one, which starts at 2 N^d r values."""
+    import torch
+    import paper_1305_4650_amd as P
+    w = W.hypradon2(128, q=5, nrhs=3)
+    N, q = w.N, w.q
+    L = N.bit_length() - 1
+    r = q * q
+    print(f"[case] last-level weights, 3 rhs, {prec}", flush=True)
+    plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
+    y, x, g = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (w.y, w.x, w.g))
+    ws = plan.workspace(w.y.shape[0], 3, prec)
+    plan.apply(y, g, x, prec, workspace=ws)
+    torch.cuda.synchronize()
+    dt = np.complex128 if prec == "fp64" else np.complex64
+    flat = ws[:3 * N * N * r * np.dtype(dt).itemsize].cpu().numpy().view(dt).astype(np.complex128)
+    del ws
+    got = np.empty((N * N, r, 3), dtype=np.complex128)
+    got[:, :, 0:2] = flat[:2 * N * N * r].reshape(N * N, r, 2)
+    got[:, :, 2] = flat[2 * N * N * r:].reshape(N * N, r)
+    delta = orc.butterfly_weights(w.phase, N, q, w.src_box, w.tgt_box, w.y, w.g, L + 1)
+    X0, X1 = leaf_nodes(w, L, orc.nodes(q))
+    slo, shi = (np.asarray(b, dtype=np.float64) for b in w.src_box)
+    cy = slo + 0.5 * (shi - slo)
+    t = tau_hypradon2(N, X0, X1, cy[0], cy[1])
+    want = delta * np.exp(-2j * np.pi * (t - np.rint(t)))[:, :, None]
+    assert_parity(got[slots(N, L)], want, tol, what=f"3 rhs {prec} last-level weights")
