@@ -245,7 +245,11 @@ int bfly_apply_batched(int n_items, const bfly_batch_item* items, int prec, void
  * With BFLY_TUNE_CACHE naming a file, records are read from it at the first
  * apply and the table is written to it after each tuning; the environment
  * overrides BFLY_UB, BFLY_KFUSE, BFLY_LDS, BFLY_KSPLIT take precedence over
- * recorded shapes.
+ * recorded shapes.  For debugging, BFLY_STOP_STAGES=n makes every single
+ * apply of the process stop after the level launches that end within its
+ * first n merge-and-split stages, without the final evaluation (the outputs
+ * are not written): the start of the workspace then holds that level's
+ * weights.
  *  adjoint              0: the arguments of bfly_apply (inputs g at the
  *                       sources, outputs f at the targets); 1: those of
  *                       bfly_apply_adjoint (inputs at the targets)

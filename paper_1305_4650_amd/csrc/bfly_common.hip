@@ -489,6 +489,13 @@ void tune_from_env(LevelArgs& la) {
     la.nsplit = (int)split.size();
     for (int i = 0; i < la.nsplit; ++i) la.split[i] = split[i];
   }
+  // BFLY_STOP_STAGES=n: stop after the launches that end within n stages
+  // (tests compare that level's weights with the oracle's)
+  static const int stop = [] {
+    const char* v = getenv("BFLY_STOP_STAGES");
+    return v ? atoi(v) : -1;
+  }();
+  if (stop >= 0) la.stop_stages = stop;
 }
 
 }  // namespace

@@ -113,6 +113,10 @@ struct LevelArgs {
   int split[16] = {0};
   int nsplit = 0;
   size_t lds_budget = 81920;     // bytes of LDS per workgroup (two workgroups per CU)
+  // debugging override (single applies): run only the level launches that
+  // end within the first stop_stages stages and no final evaluation, so that
+  // the weight buffer keeps that level's weights (-1: the whole apply)
+  int stop_stages = -1;
 };
 // Launch-shape limits of one (d, q, phase, precision): the right-hand-side
 // chunk of its kernels and the most stages a launch can fuse with chunks
