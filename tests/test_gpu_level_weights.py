@@ -29,20 +29,23 @@ import sys, numpy as np, torch
 sys.path.insert(0, {root!r})
 import paper_1305_4650_amd as P
 from paper_1305_4650_amd import workloads as W
-w = W.hypradon2(128, q=5)
+w = W.hypradon2({N}, q=5)
 plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
 y, x, g = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (w.y, w.x, w.g))
+f = np.load({fpath!r}) if {adjoint} else None
 out = {{}}
-for prec, dt in (("fp64", np.complex128), ("fp32", np.complex64)):
-    ws = plan.workspace(w.y.shape[0], 1, prec)
+for prec, dt in {precs}:
+    ws = plan.workspace((w.x if {adjoint} else w.y).shape[0], 1, prec)
     ws.zero_()
-    plan.apply(y, g, x, prec, workspace=ws)
+    if {adjoint}:
+        plan.apply_adjoint(x, torch.from_numpy(f).cuda(), y, prec, workspace=ws)
+    else:
+        plan.apply(y, g, x, prec, workspace=ws)
     torch.cuda.synchronize()
     n = w.N ** 2 * w.q ** 2 * np.dtype(dt).itemsize
     out[prec] = ws[:n].cpu().numpy().view(dt).astype(np.complex128)
 np.savez({path!r}, **out)
 """
-
 
 def tau_hypradon2(N, x0, x1, y0, y1):
     """The phase in turns in the oracle's operation order (checked below)."""
@@ -55,9 +58,10 @@ def tau_hypradon2(N, x0, x1, y0, y1):
     return m * np.sqrt(s)
 
 
-def level_layout(w, L, lvl, z):
+def level_layout(w, L, lvl, z, tgt_box=None, src_box=None):
     """For every oracle pair index at level lvl: the library's slot, the
-    target box's node coordinates and the source box's centre."""
+    target box's node coordinates and the source box's centre (boxes in the
+    roles of the apply: the plan's own, or swapped for the adjoint)."""
     N, q = w.N, w.q
     lb = L - lvl
     p = np.arange(N * N)
@@ -70,8 +74,8 @@ def level_layout(w, L, lvl, z):
             slot |= ((a[j] >> (lvl - 1 - k)) & 1) << (2 * k + j)
         for m in range(lb):
             slot |= ((b[j] >> m) & 1) << (2 * (lvl + m) + j)
-    tlo, thi = (np.asarray(v, dtype=np.float64) for v in w.tgt_box)
-    slo, shi = (np.asarray(v, dtype=np.float64) for v in w.src_box)
+    tlo, thi = (np.asarray(v, dtype=np.float64) for v in (w.tgt_box if tgt_box is None else tgt_box))
+    slo, shi = (np.asarray(v, dtype=np.float64) for v in (w.src_box if src_box is None else src_box))
     wa = (thi - tlo) / 2 ** lvl
     wb = (shi - slo) / 2 ** lb
     t = np.arange(q * q)
@@ -83,32 +87,66 @@ def level_layout(w, L, lvl, z):
     return slot, x0, x1, cb[0][:, None], cb[1][:, None]
 
 
-@pytest.mark.timeout(900)
-def test_weights_after_every_stage_match_oracle(orc, tmp_path):
-    w = W.hypradon2(128, q=5)
-    N, q = w.N, w.q
+CASES = [
+    (128, False, (("fp64", 1e-12), ("fp32", 1e-5))),
+    (128, True, (("fp64", 1e-12), ("fp32", 1e-5))),
+    (1024, False, (("fp64", 1e-12), ("fp32", 1e-5))),
+]
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("N, adjoint, precs", CASES,
+                         ids=[f"hypradon2_N{c[0]}_q5-{'adj' if c[1] else 'fwd'}" for c in CASES])
+def test_weights_after_every_stage_match_oracle(orc, tmp_path, N, adjoint, precs):
+    """Forward: the switch after floor(L/2) stages; adjoint (roles swapped,
+    phase -Phi(x, y)): after L - floor(L/2), and its row-space weights are
+    demodulated by e^{+i Phi(c_B, x^A_t)} with c_B in the plan's target box."""
+    w = W.hypradon2(N, q=5)
+    q = w.q
     L = N.bit_length() - 1
-    ls = L // 2
+    ls = L - L // 2 if adjoint else L // 2
     z = orc.nodes(q)
+    fpath = str(tmp_path / "f.npy")
+    f = None
+    if adjoint:
+        rng = np.random.default_rng(31)
+        f = rng.standard_normal((1, w.x.shape[0])) + 1j * rng.standard_normal((1, w.x.shape[0]))
+        np.save(fpath, f)
+    roles = (w.src_box, w.tgt_box) if adjoint else (w.tgt_box, w.src_box)
     for stop in range(1, L + 1):
-        print(f"[case] weights after {stop} of {L} stages (switch after {ls})", flush=True)
+        print(f"[case] N = {N} {'adjoint' if adjoint else 'forward'}: weights after {stop} of {L} stages "
+              f"(switch after {ls})", flush=True)
         path = str(tmp_path / f"stop{stop}.npz")
         env = {k: v for k, v in os.environ.items() if not k.startswith("BFLY_")}
         env.update(BFLY_KSPLIT=",".join(["1"] * L), BFLY_STOP_STAGES=str(stop))
-        r = subprocess.run([sys.executable, "-c", CODE.format(root=ROOT, path=path)], env=env,
-                           capture_output=True, text=True, timeout=300)
+        code = CODE.format(root=ROOT, path=path, N=N, adjoint=adjoint, fpath=fpath,
+                           precs=tuple((p, {"fp64": "np.complex128", "fp32": "np.complex64"}[p]) for p, _ in precs))
+        code = code.replace("'np.complex128'", "np.complex128").replace("'np.complex64'", "np.complex64")
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
         assert r.returncode == 0, r.stderr[-2000:]
-        got = np.load(path)
+        with np.load(path) as data:
+            got = {k: data[k] for k in data.files}
+        os.remove(path)
         step = stop if stop < ls else stop + 1
-        delta = orc.butterfly_weights(w.phase, N, q, w.src_box, w.tgt_box, w.y, w.g, step)[:, :, 0]
-        slot, x0, x1, cb0, cb1 = level_layout(w, L, stop, z)
+        if adjoint:
+            delta = orc.butterfly_weights(w.phase, N, q, w.src_box, w.tgt_box, w.x, f, step, adjoint=True)[:, :, 0]
+        else:
+            delta = orc.butterfly_weights(w.phase, N, q, w.src_box, w.tgt_box, w.y, w.g, step)[:, :, 0]
+        slot, x0, x1, cb0, cb1 = level_layout(w, L, stop, z, *roles)
         want = delta
         if stop >= ls:
-            t = tau_hypradon2(N, x0, x1, cb0, cb1)
+            if adjoint:  # tau of the adjoint's roles: -tau_fwd(c_B, x^A_t)
+                t = tau_hypradon2(N, cb0, cb1, x0, x1)
+                chk = lambda a, k: orc.tau(w.phase, N, [cb0[a, 0], cb1[a, 0]], [x0[a, k], x1[a, k]])
+                sign = 1.0
+            else:
+                t = tau_hypradon2(N, x0, x1, cb0, cb1)
+                chk = lambda a, k: orc.tau(w.phase, N, [x0[a, k], x1[a, k]], [cb0[a, 0], cb1[a, 0]])
+                sign = -1.0
             for i in (0, 7, t.size // 2, t.size - 1):
                 a, k = divmod(i, q * q)
-                assert t[a, k] == orc.tau(w.phase, N, [x0[a, k], x1[a, k]], [cb0[a, 0], cb1[a, 0]])
-            want = delta * np.exp(-2j * np.pi * (t - np.rint(t)))
-        for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+                assert t[a, k] == chk(a, k)
+            want = delta * np.exp(sign * 2j * np.pi * (t - np.rint(t)))
+        for prec, tol in precs:
             g = got[prec].reshape(N * N, q * q)
-            assert_parity(g[slot], want, tol, what=f"level {stop} {prec}")
+            assert_parity(g[slot], want, tol, what=f"N = {N} level {stop} {prec}")
