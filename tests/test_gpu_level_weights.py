@@ -1,10 +1,9 @@
 """Level-by-level parity: the weights after every merge-and-split stage.
 
-A fresh process applies the 2-D hyperbolic-Radon workload (N = 128, q = 5:
-three column-space stages, the switch, four row-space stages) with one stage
-per launch (BFLY_KSPLIT) and stops after the first n stages (BFLY_STOP_STAGES,
-read once per process), so that the start of the workspace holds the weights
-of level n; the oracle's weights after the same step
+A fresh process applies a 2-D workload (hyperbolic Radon at N = 128 and at
+full C2 size, Fourier at C1 size) with one stage per launch (BFLY_KSPLIT)
+and stops after the first n stages (BFLY_STOP_STAGES, read once per
+process), so that the start of the workspace holds the weights of level n; the oracle's weights after the same step
 (orc_butterfly_dump) are the reference.  Level n's slot of the pair (A, B)
 holds A's split bits, coarsest first, in its low n digits and B in Morton
 order, finest digit lowest, in the high L - n digits.  Column-space weights
@@ -29,7 +28,7 @@ import sys, numpy as np, torch
 sys.path.insert(0, {root!r})
 import paper_1305_4650_amd as P
 from paper_1305_4650_amd import workloads as W
-w = W.hypradon2({N}, q=5)
+w = {make}
 plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
 y, x, g = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (w.y, w.x, w.g))
 f = np.load({fpath!r}) if {adjoint} else None
@@ -56,6 +55,15 @@ def tau_hypradon2(N, x0, x1, y0, y1):
     s = a + e
     m = float(N) * x0
     return m * np.sqrt(s)
+
+
+def tau_fourier(N, x0, x1, y0, y1):
+    """x . y in turns in the oracle's operation order."""
+    s = x0 * y0
+    return s + x1 * y1
+
+
+TAU = {"hypradon2": tau_hypradon2, "fourier": tau_fourier}
 
 
 def level_layout(w, L, lvl, z, tgt_box=None, src_box=None):
@@ -87,22 +95,26 @@ def level_layout(w, L, lvl, z, tgt_box=None, src_box=None):
     return slot, x0, x1, cb[0][:, None], cb[1][:, None]
 
 
+BOTH = (("fp64", 1e-12), ("fp32", 1e-5))
 CASES = [
-    (128, False, (("fp64", 1e-12), ("fp32", 1e-5))),
-    (128, True, (("fp64", 1e-12), ("fp32", 1e-5))),
-    (1024, False, (("fp64", 1e-12), ("fp32", 1e-5))),
+    ("hypradon2_N128_q5", "W.hypradon2(128, q=5)", False, BOTH),
+    ("hypradon2_N128_q5", "W.hypradon2(128, q=5)", True, BOTH),
+    ("C1_fourier2d_N64_q5", "W.C1()", False, BOTH),
+    ("C1_fourier2d_N64_q5", "W.C1()", True, BOTH),
+    ("C2_hypradon2_N1024_q5", "W.C2()", False, BOTH),
 ]
 
 
 @pytest.mark.timeout(1200)
-@pytest.mark.parametrize("N, adjoint, precs", CASES,
-                         ids=[f"hypradon2_N{c[0]}_q5-{'adj' if c[1] else 'fwd'}" for c in CASES])
-def test_weights_after_every_stage_match_oracle(orc, tmp_path, N, adjoint, precs):
+@pytest.mark.parametrize("name, make, adjoint, precs", CASES,
+                         ids=[f"{c[0]}-{'adj' if c[2] else 'fwd'}" for c in CASES])
+def test_weights_after_every_stage_match_oracle(orc, tmp_path, name, make, adjoint, precs):
     """Forward: the switch after floor(L/2) stages; adjoint (roles swapped,
     phase -Phi(x, y)): after L - floor(L/2), and its row-space weights are
     demodulated by e^{+i Phi(c_B, x^A_t)} with c_B in the plan's target box."""
-    w = W.hypradon2(N, q=5)
-    q = w.q
+    w = eval(make, {"W": W})
+    N, q = w.N, w.q
+    tau = TAU[w.phase]
     L = N.bit_length() - 1
     ls = L - L // 2 if adjoint else L // 2
     z = orc.nodes(q)
@@ -114,12 +126,12 @@ def test_weights_after_every_stage_match_oracle(orc, tmp_path, N, adjoint, precs
         np.save(fpath, f)
     roles = (w.src_box, w.tgt_box) if adjoint else (w.tgt_box, w.src_box)
     for stop in range(1, L + 1):
-        print(f"[case] N = {N} {'adjoint' if adjoint else 'forward'}: weights after {stop} of {L} stages "
+        print(f"[case] {name} {'adjoint' if adjoint else 'forward'}: weights after {stop} of {L} stages "
               f"(switch after {ls})", flush=True)
         path = str(tmp_path / f"stop{stop}.npz")
         env = {k: v for k, v in os.environ.items() if not k.startswith("BFLY_")}
         env.update(BFLY_KSPLIT=",".join(["1"] * L), BFLY_STOP_STAGES=str(stop))
-        code = CODE.format(root=ROOT, path=path, N=N, adjoint=adjoint, fpath=fpath,
+        code = CODE.format(root=ROOT, path=path, make=make, adjoint=adjoint, fpath=fpath,
                            precs=tuple((p, {"fp64": "np.complex128", "fp32": "np.complex64"}[p]) for p, _ in precs))
         code = code.replace("'np.complex128'", "np.complex128").replace("'np.complex64'", "np.complex64")
         r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
@@ -136,11 +148,11 @@ def test_weights_after_every_stage_match_oracle(orc, tmp_path, N, adjoint, precs
         want = delta
         if stop >= ls:
             if adjoint:  # tau of the adjoint's roles: -tau_fwd(c_B, x^A_t)
-                t = tau_hypradon2(N, cb0, cb1, x0, x1)
+                t = tau(N, cb0, cb1, x0, x1)
                 chk = lambda a, k: orc.tau(w.phase, N, [cb0[a, 0], cb1[a, 0]], [x0[a, k], x1[a, k]])
                 sign = 1.0
             else:
-                t = tau_hypradon2(N, x0, x1, cb0, cb1)
+                t = tau(N, x0, x1, cb0, cb1)
                 chk = lambda a, k: orc.tau(w.phase, N, [x0[a, k], x1[a, k]], [cb0[a, 0], cb1[a, 0]])
                 sign = -1.0
             for i in (0, 7, t.size // 2, t.size - 1):
@@ -149,4 +161,4 @@ def test_weights_after_every_stage_match_oracle(orc, tmp_path, N, adjoint, precs
             want = delta * np.exp(sign * 2j * np.pi * (t - np.rint(t)))
         for prec, tol in precs:
             g = got[prec].reshape(N * N, q * q)
-            assert_parity(g[slot], want, tol, what=f"N = {N} level {stop} {prec}")
+            assert_parity(g[slot], want, tol, what=f"{name} level {stop} {prec}")
