@@ -162,3 +162,86 @@ def test_weights_after_every_stage_match_oracle(orc, tmp_path, name, make, adjoi
         for prec, tol in precs:
             g = got[prec].reshape(N * N, q * q)
             assert_parity(g[slot], want, tol, what=f"{name} level {stop} {prec}")
+
+
+def level_layout_nd(w, L, lvl, z, d, tgt_box, src_box):
+    """level_layout in d dimensions: slot, target nodes [pair][t][j] and
+    source centres [pair][j] (t = sum_j t_j q^j)."""
+    N, q = w.N, w.q
+    lb = L - lvl
+    p = np.arange(N ** d)
+    a_lin, b_lin = p >> (d * lb), p & ((1 << (d * lb)) - 1)
+    a = [(a_lin >> (lvl * j)) & ((1 << lvl) - 1) for j in range(d)]
+    b = [(b_lin >> (lb * j)) & ((1 << lb) - 1) for j in range(d)]
+    slot = np.zeros(N ** d, dtype=np.int64)
+    for j in range(d):
+        for k in range(lvl):
+            slot |= ((a[j] >> (lvl - 1 - k)) & 1) << (d * k + j)
+        for m in range(lb):
+            slot |= ((b[j] >> m) & 1) << (d * (lvl + m) + j)
+    tlo, thi = (np.asarray(v, dtype=np.float64) for v in tgt_box)
+    slo, shi = (np.asarray(v, dtype=np.float64) for v in src_box)
+    wa, wb = (thi - tlo) / 2 ** lvl, (shi - slo) / 2 ** lb
+    t = np.arange(q ** d)
+    x = np.empty((N ** d, q ** d, d))
+    cb = np.empty((N ** d, d))
+    for j in range(d):
+        t_j = (t // q ** j) % q
+        x[:, :, j] = (tlo[j] + (a[j] + 0.5) * wa[j])[:, None] + (0.5 * wa[j]) * z[t_j][None, :]
+        cb[:, j] = slo[j] + (b[j] + 0.5) * wb[j]
+    return slot, x, cb
+
+
+ND_CASES = [("genradon3_N16_q4", "W.genradon3(16, q=4)", False), ("genradon3_N16_q4", "W.genradon3(16, q=4)", True),
+            ("fourier1d_N64_q8", "W.fourier_grid(64, d=1, q=8)", False)]
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("name, make, adjoint", ND_CASES, ids=[f"{c[0]}-{'adj' if c[2] else 'fwd'}" for c in ND_CASES])
+def test_nd_weights_after_every_stage_match_oracle(orc, tmp_path, name, make, adjoint):
+    """3-D (generalized Radon; demodulation factors from the oracle's own
+    phase, node by node) and 1-D (Fourier), every level."""
+    w = eval(make, {"W": W})
+    N, q, d = w.N, w.q, w.d
+    L = N.bit_length() - 1
+    ls = L - L // 2 if adjoint else L // 2
+    r = q ** d
+    z = orc.nodes(q)
+    fpath = str(tmp_path / "f.npy")
+    f = None
+    if adjoint:
+        rng = np.random.default_rng(37)
+        f = rng.standard_normal((1, w.x.shape[0])) + 1j * rng.standard_normal((1, w.x.shape[0]))
+        np.save(fpath, f)
+    roles = (w.src_box, w.tgt_box) if adjoint else (w.tgt_box, w.src_box)
+    for stop in range(1, L + 1):
+        print(f"[case] {name} {'adjoint' if adjoint else 'forward'}: weights after {stop} of {L} stages "
+              f"(switch after {ls})", flush=True)
+        path = str(tmp_path / f"stop{stop}.npz")
+        env = {k: v for k, v in os.environ.items() if not k.startswith("BFLY_")}
+        env.update(BFLY_KSPLIT=",".join(["1"] * L), BFLY_STOP_STAGES=str(stop))
+        code = CODE.format(root=ROOT, path=path, make=make, adjoint=adjoint, fpath=fpath,
+                           precs=(("fp64", "np.complex128"), ("fp32", "np.complex64")))
+        code = code.replace("'np.complex128'", "np.complex128").replace("'np.complex64'", "np.complex64")
+        code = code.replace("w.N ** 2 * w.q ** 2", "w.N ** w.d * w.q ** w.d")
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+        assert res.returncode == 0, res.stderr[-2000:]
+        with np.load(path) as data:
+            got = {k: data[k] for k in data.files}
+        os.remove(path)
+        step = stop if stop < ls else stop + 1
+        if adjoint:
+            delta = orc.butterfly_weights(w.phase, N, q, w.src_box, w.tgt_box, w.x, f, step, adjoint=True)[:, :, 0]
+        else:
+            delta = orc.butterfly_weights(w.phase, N, q, w.src_box, w.tgt_box, w.y, w.g, step)[:, :, 0]
+        slot, x, cb = level_layout_nd(w, L, stop, z, d, *roles)
+        want = delta
+        if stop >= ls:
+            if adjoint:
+                t = np.array([[orc.tau(w.phase, N, cb[a], x[a, k]) for k in range(r)] for a in range(N ** d)])
+                want = delta * np.exp(2j * np.pi * (t - np.rint(t)))
+            else:
+                t = np.array([[orc.tau(w.phase, N, x[a, k], cb[a]) for k in range(r)] for a in range(N ** d)])
+                want = delta * np.exp(-2j * np.pi * (t - np.rint(t)))
+        for prec, tol in BOTH:
+            assert_parity(got[prec].reshape(N ** d, r)[slot], want, tol, what=f"{name} level {stop} {prec}")
