@@ -23,11 +23,15 @@ import numpy.polynomial.chebyshev as npcheb
 import pytest
 
 CASES = [
-    # phase, d, N, q, switch level (-1: the default floor(L/2))
-    ("hypradon2", 2, 16, 4, -1),
-    ("fourier", 1, 64, 5, -1),
-    ("fourier", 2, 8, 3, 1),
-    ("genradon3", 3, 4, 3, -1),
+    # phase, d, N, q, switch level (-1: the default), adjoint
+    ("hypradon2", 2, 16, 4, -1, False),
+    ("fourier", 1, 64, 5, -1, False),
+    ("fourier", 2, 8, 3, 1, False),
+    ("genradon3", 3, 4, 3, -1, False),
+    # odd L, where the adjoint's mirror switch level differs from floor(L/2)
+    ("hypradon2", 2, 32, 3, -1, True),
+    ("fourier", 1, 128, 5, -1, True),
+    ("genradon3", 3, 8, 3, -1, True),
 ]
 
 
@@ -35,10 +39,12 @@ class Geo:
     """Box geometry of the dumps: level-lvl target boxes split the target box
     into 2^lvl per dimension, source boxes into 2^(L-lvl)."""
 
-    def __init__(self, orc, phase, d, N, q, sw, rng):
+    def __init__(self, orc, phase, d, N, q, sw, adjoint, rng):
         self.orc, self.phase, self.d, self.N, self.q = orc, phase, d, N, q
+        self.adjoint = adjoint
         self.L = N.bit_length() - 1
-        self.ls = self.L // 2 if sw < 0 else sw
+        # the adjoint's default switch is the mirror level L - floor(L/2)
+        self.ls = (self.L - self.L // 2 if adjoint else self.L // 2) if sw < 0 else sw
         self.sw = sw
         self.slo = rng.uniform(-0.5, 0.2, d)
         self.shi = self.slo + rng.uniform(0.6, 1.2, d)
@@ -78,15 +84,25 @@ class Geo:
     def grid(self, c, w):
         return c + 0.5 * w * self.z[self.tidx]
 
+    def plan_boxes(self):
+        """(source box, target box) of the plan: the roles' boxes, swapped
+        for the adjoint (its sources lie in the plan's target box)."""
+        roles = ((self.slo, self.shi), (self.tlo, self.thi))
+        return roles[::-1] if self.adjoint else roles
+
     def e(self, x, y):
-        """e^{i Phi(x, y)} for one target-role x and rows y (or the reverse)."""
+        """The kernel between target-role x and source-role y, one of them a
+        single point: e^{i Phi(x, y)}, or for the adjoint e^{-i Phi(y, x)}."""
         x, y = np.atleast_2d(x), np.atleast_2d(y)
         if len(x) == 0 or len(y) == 0:
             return np.zeros(0, dtype=complex)
         n = max(len(x), len(y))
         x = np.broadcast_to(x, (n, self.d))
         y = np.broadcast_to(y, (n, self.d))
-        tau = np.array([self.orc.tau(self.phase, self.N, xi, yi) for xi, yi in zip(x, y)])
+        if self.adjoint:
+            tau = -np.array([self.orc.tau(self.phase, self.N, yi, xi) for xi, yi in zip(x, y)])
+        else:
+            tau = np.array([self.orc.tau(self.phase, self.N, xi, yi) for xi, yi in zip(x, y)])
         return np.exp(2j * np.pi * (tau - np.rint(tau)))
 
     def interp(self, c, w, vals, x):
@@ -104,9 +120,8 @@ class Geo:
         return vand(u) @ coef
 
     def weights(self, pts, g, step):
-        return self.orc.butterfly_weights(self.phase, self.N, self.q, (self.slo, self.shi),
-                                          (self.tlo, self.thi), pts, g, step,
-                                          switch_level=self.sw)
+        return self.orc.butterfly_weights(self.phase, self.N, self.q, *self.plan_boxes(), pts, g, step,
+                                          adjoint=self.adjoint, switch_level=self.sw)
 
 
 def make(orc, case, seed, n=300, nrhs=2):
@@ -131,7 +146,7 @@ def close(a, b, scale, tol=1e-11):
     assert err <= tol * scale, (err, scale)
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}")
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}{'_adj' if c[5] else ''}")
 def test_single_source_support(orc, case):
     geo, pts, g = make(orc, case, 11, n=1, nrhs=1)
     leaf = orc.bin_points(pts, geo.slo, geo.shi, geo.N)[0]
@@ -145,7 +160,7 @@ def test_single_source_support(orc, case):
         assert nz.tolist() == want, step
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}")
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}{'_adj' if c[5] else ''}")
 def test_initialisation_keeps_moments(orc, case):
     """Step 0: sum_t y_t^m e^{i Phi(c_X, y_t)} delta_t equals the same moment of
     the leaf's own modulated sources, X the root target box."""
@@ -164,7 +179,7 @@ def test_initialisation_keeps_moments(orc, case):
         close(lhs, rhs, 1.0 + np.abs(g[:, inside]).sum())
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}")
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}{'_adj' if c[5] else ''}")
 def test_column_stages_keep_moments(orc, case):
     """Column stage l -> l+1: for child target box A' of P and merged source box
     B' with children B_c, the modulated moments about c_A' of the new weights
@@ -191,7 +206,7 @@ def test_column_stages_keep_moments(orc, case):
         prev = cur
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}")
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}{'_adj' if c[5] else ''}")
 def test_switch_is_the_dense_node_sum(orc, case):
     geo, pts, g = make(orc, case, 14)
     before = geo.weights(pts, g, geo.ls)
@@ -205,7 +220,7 @@ def test_switch_is_the_dense_node_sum(orc, case):
         close(after[pair], K @ before[pair], scale)
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}")
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}{'_adj' if c[5] else ''}")
 def test_row_stages_interpolate_the_parent(orc, case):
     """Row stage l -> l+1: the weights of (A', B') at A's nodes x are
     sum_c e^{i Phi(x, c_Bc)} h_c(x), h_c the parent's interpolant of its
@@ -232,7 +247,7 @@ def test_row_stages_interpolate_the_parent(orc, case):
             close(cur[pair], want, scale * 2 ** geo.d * 8, tol=1e-10)
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}")
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}_d{c[1]}_N{c[2]}_q{c[3]}_s{c[4]}{'_adj' if c[5] else ''}")
 def test_final_evaluation_of_the_last_weights(orc, case):
     """The apply's output at x in leaf A is e^{i Phi(x, c_Y)} times the leaf's
     interpolant of its last weights demodulated by e^{-i Phi(x^A_t, c_Y)},
@@ -240,8 +255,8 @@ def test_final_evaluation_of_the_last_weights(orc, case):
     geo, pts, g = make(orc, case, 16)
     rng = np.random.default_rng(17)
     xs = geo.tlo + (geo.thi - geo.tlo) * rng.random((40, geo.d))
-    out = orc.butterfly(geo.phase, geo.N, geo.q, (geo.slo, geo.shi), (geo.tlo, geo.thi),
-                        pts, g, xs, switch_level=geo.sw)
+    out = orc.butterfly(geo.phase, geo.N, geo.q, *geo.plan_boxes(), pts, g, xs,
+                        adjoint=geo.adjoint, switch_level=geo.sw)
     last = geo.weights(pts, g, geo.L + 1)
     cY, _ = geo.sbox(geo.L, np.zeros(geo.d, dtype=int))
     tleaf = orc.bin_points(xs, geo.tlo, geo.thi, geo.N)
@@ -263,7 +278,7 @@ def test_last_weights_approach_the_potentials(orc):
     errs = {}
     for q in (5, 7, 9, 11):
         rng = np.random.default_rng(18)
-        geo = Geo(orc, "hypradon2", 2, 16, q, -1, rng)
+        geo = Geo(orc, "hypradon2", 2, 16, q, -1, False, rng)
         geo.slo, geo.shi = np.full(2, 1.0), np.full(2, 2.0)
         geo.tlo, geo.thi = np.zeros(2), np.ones(2)
         pts = geo.slo + rng.random((300, 2))
