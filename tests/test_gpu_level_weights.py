@@ -1,10 +1,12 @@
 """Level-by-level parity: the weights after every merge-and-split stage.
 
-A fresh process applies a 2-D workload (hyperbolic Radon at N = 128 and at
-full C2 size, Fourier at C1 size) with one stage per launch (BFLY_KSPLIT)
+A fresh process applies a workload with one stage per launch (BFLY_KSPLIT)
 and stops after the first n stages (BFLY_STOP_STAGES, read once per
-process), so that the start of the workspace holds the weights of level n; the oracle's weights after the same step
-(orc_butterfly_dump) are the reference.  Level n's slot of the pair (A, B)
+process), so that the start of the workspace holds the weights of level n;
+the oracle's weights after the same step (orc_butterfly_dump) are the
+reference.  Workloads: 2-D hyperbolic Radon at N = 128 (dense, sparse
+sources, sparse targets) and at full C2 size, 2-D Fourier at C1 size, 3-D
+generalized Radon at N = 16, 1-D Fourier at N = 64; forward and adjoint.  Level n's slot of the pair (A, B)
 holds A's split bits, coarsest first, in its low n digits and B in Morton
 order, finest digit lowest, in the high L - n digits.  Column-space weights
 are the equivalent sources themselves; from the switch on the library keeps
@@ -33,7 +35,8 @@ plan = P.Plan(w.d, w.N, w.src_box, w.tgt_box, w.phase, w.q)
 y, x, g = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (w.y, w.x, w.g))
 f = np.load({fpath!r}) if {adjoint} else None
 out = {{}}
-for prec, dt in {precs}:
+for prec in {precs}:
+    dt = np.complex128 if prec == "fp64" else np.complex64
     ws = plan.workspace((w.x if {adjoint} else w.y).shape[0], 1, prec)
     ws.zero_()
     if {adjoint}:
@@ -41,10 +44,11 @@ for prec, dt in {precs}:
     else:
         plan.apply(y, g, x, prec, workspace=ws)
     torch.cuda.synchronize()
-    n = w.N ** 2 * w.q ** 2 * np.dtype(dt).itemsize
+    n = w.N ** w.d * w.q ** w.d * np.dtype(dt).itemsize
     out[prec] = ws[:n].cpu().numpy().view(dt).astype(np.complex128)
 np.savez({path!r}, **out)
 """
+
 
 def tau_hypradon2(N, x0, x1, y0, y1):
     """The phase in turns in the oracle's operation order (checked below)."""
@@ -139,8 +143,7 @@ def test_weights_after_every_stage_match_oracle(orc, tmp_path, name, make, adjoi
         env = {k: v for k, v in os.environ.items() if not k.startswith("BFLY_")}
         env.update(BFLY_KSPLIT=",".join(["1"] * L), BFLY_STOP_STAGES=str(stop))
         code = CODE.format(root=ROOT, path=path, make=make, adjoint=adjoint, fpath=fpath,
-                           precs=tuple((p, {"fp64": "np.complex128", "fp32": "np.complex64"}[p]) for p, _ in precs))
-        code = code.replace("'np.complex128'", "np.complex128").replace("'np.complex64'", "np.complex64")
+                           precs=[p for p, _ in precs])
         r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
         assert r.returncode == 0, r.stderr[-2000:]
         with np.load(path) as data:
@@ -232,9 +235,7 @@ def test_nd_weights_after_every_stage_match_oracle(orc, tmp_path, name, make, ad
         env = {k: v for k, v in os.environ.items() if not k.startswith("BFLY_")}
         env.update(BFLY_KSPLIT=",".join(["1"] * L), BFLY_STOP_STAGES=str(stop))
         code = CODE.format(root=ROOT, path=path, make=make, adjoint=adjoint, fpath=fpath,
-                           precs=(("fp64", "np.complex128"), ("fp32", "np.complex64")))
-        code = code.replace("'np.complex128'", "np.complex128").replace("'np.complex64'", "np.complex64")
-        code = code.replace("w.N ** 2 * w.q ** 2", "w.N ** w.d * w.q ** w.d")
+                           precs=[p for p, _ in BOTH])
         res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
         assert res.returncode == 0, res.stderr[-2000:]
         with np.load(path) as data:
